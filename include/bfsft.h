@@ -1,0 +1,168 @@
+/*
+ * bfsft - butterfly sparse Fourier transform on one MI355X (gfx950).
+ *
+ * Computes, for target points x_i (i in I) and source points k_j (j in J) in
+ * [0, N]^d (d = 2 or 3) and complex sources f_j,
+ *
+ *     u_i = sum_j exp(+2 pi i x_i . k_j / N) f_j            (Section 1, eq. 1)
+ *
+ * with the butterfly algorithm of Section 2.2: quadtrees (octrees) T_X and
+ * T_K with leaves of width rho = N / 2^L, L = ceil(log2 N) (step 1); p^d
+ * equivalent-source / check grids per box pair with w^A w^B = rho N
+ * (Section 2.1); leaf initialisation (step 2); the level-by-level sweep up
+ * T_K (step 3); evaluation at the leaves of T_X (step 4).  The result is an
+ * approximation of eq. (1) whose accuracy is set by p (Theorem 2.1, Table 1:
+ * about 2e-3, 1e-5, 5e-8 relative l2 at p = 5, 7, 9 in 2D).
+ *
+ * Memory model.  Every pointer argument marked "device" is a HIP device
+ * pointer on the current device; "host" pointers are ordinary CPU memory.
+ * Complex numbers are interleaved (re, im) float64 pairs.  Point arrays are
+ * row-major [n][d] float64.  All device work is enqueued on the stream given
+ * at plan creation; bfsft_execute* are asynchronous with respect to the host
+ * and ordered on that stream.  A plan is not safe for concurrent use from
+ * several host threads.
+ *
+ * Errors.  Functions return BFSFT_OK (0) or a negative status; nothing is
+ * thrown or aborted across this interface.  bfsft_last_error() returns a
+ * thread-local message describing the most recent failure.  On failure of a
+ * *_create call, *out is set to NULL and nothing is leaked.
+ */
+#ifndef BFSFT_H
+#define BFSFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BFSFT_OK        0
+#define BFSFT_EINVAL   -1   /* bad argument: d, p, N, counts, NULL pointers, precision */
+#define BFSFT_EDOMAIN  -2   /* a point coordinate is NaN/inf or outside [0, N] */
+#define BFSFT_ENOMEM   -3   /* device allocation failed or BFSFT_MAX_DEVICE_BYTES exceeded */
+#define BFSFT_EDEVICE  -4   /* a HIP runtime call failed (message in bfsft_last_error) */
+
+/* Arithmetic of the translation sweep.  Leaf initialisation, phases and the
+ * final evaluation always run in FP64; inputs and outputs are complex128. */
+#define BFSFT_FP64   0  /* FP64 state in HBM, FP64 arithmetic                */
+#define BFSFT_MIXED  1  /* FP32 state in HBM, FP64 arithmetic in registers   */
+#define BFSFT_FP32   2  /* FP32 state in HBM, FP32 arithmetic                */
+
+#define BFSFT_MAX_LEVELS 32
+
+typedef struct bfsft_plan bfsft_plan;
+
+/* Sizes of a plan (filled by bfsft_plan_info). */
+typedef struct {
+    int d, p, precision, levels;          /* levels = L */
+    int64_t N, nx, nk;
+    double rho;                           /* leaf width N / 2^L */
+    int64_t x_boxes[BFSFT_MAX_LEVELS + 1];/* non-empty T_X boxes at level m = 0..L */
+    int64_t k_boxes[BFSFT_MAX_LEVELS + 1];/* non-empty T_K boxes at level m = 0..L */
+    int64_t pairs[BFSFT_MAX_LEVELS + 1];  /* box pairs at T_K level l: x_boxes[L-l] * k_boxes[l] */
+    double sweep_bytes;                   /* algorithmic HBM bytes of the sweep (read + write
+                                             of every level's state, once) */
+    double sweep_flops;                   /* algorithmic flops of the sweep: per output pair,
+                                             2^d * d * p^(d+1) complex multiply-adds x 8 */
+    int64_t device_bytes;                 /* device memory owned by the plan */
+    int64_t transforms;                   /* 1, or the count of a batched plan */
+} bfsft_info;
+
+/*
+ * Create a plan (step 1 of Section 2.2: the trees, plus the operator tables).
+ *
+ *   out        host: receives the plan handle.
+ *   d          2 or 3.
+ *   N          frequency bound, 2 <= N <= 2^24 (2D) or 2^16 (3D).
+ *   p          equivalent-grid size per axis (Section 2.1), 3 <= p <= 12 in
+ *              2D, 3 <= p <= 8 in 3D (p = 2 makes the matching system
+ *              singular).
+ *   precision  BFSFT_FP64, BFSFT_MIXED or BFSFT_FP32.
+ *   x, nx      device, [nx][d] targets in [0, N]^d; nx >= 0 (NULL iff nx == 0).
+ *   k, nk      device, [nk][d] sources in [0, N]^d; nk >= 0 (NULL iff nk == 0).
+ *   stream     hipStream_t (NULL = default stream) used for all work of the plan.
+ *
+ * The points are copied; the caller may free x and k when this returns (the
+ * call synchronises the stream).  Box index of a point along an axis:
+ * min(floor(x * 2^L / N), 2^L - 1) in IEEE FP64 (half-open boxes).
+ * Environment: BFSFT_MAX_DEVICE_BYTES caps the plan's device memory.
+ */
+int bfsft_plan_create(bfsft_plan **out, int d, int64_t N, int p, int precision,
+                      const double *x, int64_t nx, const double *k, int64_t nk,
+                      void *stream);
+
+/*
+ * Execute steps 2-4 of Section 2.2 for sources f.
+ *   f   device, [nk] complex128 (original source order), read only.
+ *   u   device, [nx] complex128 (original target order), overwritten; must
+ *       not alias f.
+ * nk == 0 gives u = 0; nx == 0 is a no-op.  Asynchronous on the plan stream.
+ */
+int bfsft_execute(bfsft_plan *plan, const double *f, double *u);
+
+/* Release a plan and all its device memory (synchronises its stream).
+ * NULL is a no-op. */
+void bfsft_destroy(bfsft_plan *plan);
+
+/* Static description of a status code. */
+const char *bfsft_strerror(int status);
+
+/* Thread-local message of the last failure in this thread ("" if none). */
+const char *bfsft_last_error(void);
+
+/* Sizes and algorithmic work of a plan (host struct). */
+int bfsft_plan_info(const bfsft_plan *plan, bfsft_info *out);
+
+/*
+ * Box coordinates of level m of T_X (side 0) or T_K (side 1), in the order
+ * the plan stores them (Morton order).
+ *   coords  host, [count][d] int64, count = x_boxes[m] or k_boxes[m].
+ */
+int bfsft_plan_boxes(const bfsft_plan *plan, int side, int m, int64_t *coords);
+
+/*
+ * Parity probe: run bfsft_execute and also export the check potentials
+ * u^{AB}_l = sum over sources of B of exp(2 pi i x^A_l . k / N) f, as
+ * reproduced by the sweep at T_K level `level` (Section 2.1: the potentials
+ * at the p^d check points x^A_l of A; for level L these are the exact leaf
+ * potentials of step 2).
+ *   pot  device, [x_boxes[L-level]][k_boxes[level]][p^d] complex128, boxes in
+ *        the order of bfsft_plan_boxes, grid index row-major (axis 1 slowest).
+ */
+int bfsft_execute_probe(bfsft_plan *plan, const double *f, double *u,
+                        int level, double *pot);
+
+/* One problem of a batched plan (all points in device memory). */
+typedef struct {
+    int64_t N;
+    const double *x; int64_t nx;   /* device, [nx][d] */
+    const double *k; int64_t nk;   /* device, [nk][d] */
+} bfsft_problem;
+
+/*
+ * Batched plan: `count` independent transforms of the same d, p and
+ * precision but their own N and points.  Execution runs sweep step
+ * s = 1 .. max_t L_t for all transforms still active in one persistent launch
+ * per step (transform t works on its T_K level L_t - s), all captured in one
+ * HIP graph.
+ *   probs  host, [count] problem descriptors (device point pointers).
+ * Sources and outputs are packed: transform t reads f_packed at offset
+ * sum_{t'<t} nk_{t'} and writes u_packed at offset sum_{t'<t} nx_{t'}.
+ */
+int bfsft_plan_create_batched(bfsft_plan **out, int count, const bfsft_problem *probs,
+                              int d, int p, int precision, void *stream);
+
+/* Execute a batched plan (one graph launch on the plan stream).
+ *   f_packed  device, [sum nk] complex128.
+ *   u_packed  device, [sum nx] complex128, overwritten. */
+int bfsft_execute_batched(bfsft_plan *plan, const double *f_packed, double *u_packed);
+
+/* Execute a batched plan without the graph and without the persistent
+ * multi-transform launches: each transform's steps are launched one after
+ * another (the per-transform baseline the batched path is compared with). */
+int bfsft_execute_batched_serial(bfsft_plan *plan, const double *f_packed, double *u_packed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFSFT_H */
