@@ -1,0 +1,113 @@
+// Internal declarations of the bfsft library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bfsft.h"
+
+namespace bfsft {
+
+// ---------------------------------------------------------------- errors --
+struct Error {
+    int status;
+    std::string msg;
+};
+
+void set_last_error(const std::string &m);
+
+#define BF_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::bfsft::Error{BFSFT_EDEVICE, std::string(#call) + ": " +           \
+                                                    hipGetErrorString(e_)};           \
+    } while (0)
+
+// ------------------------------------------------------------ allocation --
+// Device allocations of a plan are tracked so that BFSFT_MAX_DEVICE_BYTES can
+// be enforced before any allocation is made.
+struct Arena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    int64_t cap = -1;  // -1: no cap
+    void *alloc(size_t n);
+    void release();
+};
+
+// -------------------------------------------------------------- tree ------
+// One quadtree / octree over a point set, built on the device (step 1).
+// Level m holds the non-empty boxes of width N / 2^m in Morton order.
+struct Tree {
+    int d = 0, L = 0;
+    int64_t npts = 0;
+    std::vector<int64_t> count;        // [L+1] boxes per level
+    std::vector<uint64_t *> keys;      // [L+1] device, Morton keys of level m
+    std::vector<int32_t *> child_beg;  // [L] device, level m: [count[m]+1] first child in level m+1
+    std::vector<std::vector<int32_t>> child_beg_host;  // same, host copies (tiling)
+    int32_t *perm = nullptr;           // device [npts]: Morton-sorted position -> original index
+    int32_t *leaf_beg = nullptr;       // device [count[L]+1]: sorted points of each leaf
+    int32_t *leaf_of = nullptr;        // device [npts]: leaf of each point, original order
+    double *local = nullptr;           // device [npts][d]: x - rho*leaf_index, original order
+};
+
+void build_tree(Tree &t, const double *pts_dev, int64_t n, int d, int L, int64_t N,
+                Arena &arena, hipStream_t s);
+
+// device scan used by the tree build (exclusive, uint32); returns nothing,
+// temporary storage from `arena_tmp`
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s,
+                        std::vector<void *> &tmp);
+
+// ------------------------------------------------------------- kernels ----
+// Operator tables of one leaf width rho (Section 2.1, as interpolation rows).
+struct Tables {
+    double *L64 = nullptr;   // [2][p][p] complex: Lagrange rows L_t
+    float *L32 = nullptr;
+    double *PH64 = nullptr;  // [2][p] complex: phase of a child at offset s = 1
+    float *PH32 = nullptr;
+    double *nodes = nullptr; // [p] complex  Z_k (unused by kernels; kept for probes)
+    double *bary = nullptr;  // [p] complex  barycentric weights of the nodes
+    double *node_turns = nullptr; // [p] real  rho*k/q^2
+};
+
+void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t s);
+
+// per-level arguments of the translation kernels
+struct LevelArgs {
+    const void *in;          // state of T_K level l+1, rows a' (T_X level L-l-1)
+    void *out;               // state of T_K level l,   rows a  (T_X level L-l)
+    int64_t in_row;          // boxes per input row  = count_K[l+1]
+    int64_t out_row;         // boxes per output row = count_K[l]
+    const int32_t *x_cb;     // T_X level L-l-1: children range in level L-l, [nap+1]
+    const uint64_t *x_keys;  // T_X level L-l keys (child position t)
+    const int32_t *k_cb;     // T_K level l: children range in level l+1
+    const uint64_t *k_keys;  // T_K level l+1 keys (child position s)
+    const int2 *tiles;       // [ntile] b ranges
+    int ntile;
+    int64_t nap;             // rows a'
+    const double *sig;       // [nap][d] complex exp(2 pi i rho i_{A'}) or null (rho == 1)
+};
+
+struct Launch {
+    int d, p, precision;
+    const Tables *tb;
+    hipStream_t stream;
+};
+
+int translate_max_inputs(int d, int p, int precision);
+void launch_translate(const Launch &c, const LevelArgs &a);
+void launch_leaf(const Launch &c, const double *f, const Tree &tk, double rho, void *state);
+void launch_final(const Launch &c, const void *state, const Tree &tx, double rho, int64_t nx,
+                  double *u);
+void launch_export(const Launch &c, const void *state, const uint64_t *xkeys, int64_t nA,
+                   const uint64_t *kkeys, int64_t nB, int lvl, int L, int64_t N, double *pot);
+void launch_zero_c128(double *u, int64_t n, hipStream_t s);
+void launch_sigma(const uint64_t *keys, int64_t n, int d, int m, int L, int64_t N,
+                  double *sig, hipStream_t s);
+
+}  // namespace bfsft

@@ -1,0 +1,665 @@
+// Steps 2-4 of Section 2.2 on gfx950: leaf initialisation, the level sweep
+// and the evaluation at the leaves of T_X.
+//
+// State representation.  The paper stores equivalent charges f^{AB}
+// (Section 2.1) and recomputes check potentials u^{AB} = M f^{AB} from the
+// children at every level.  Here the state of a box pair is its check
+// potential itself, with B's corner phase divided out:
+//
+//     w^{AB}_l = exp(-2 pi i x^A_l . c^B / N) u^{AB}_l ,   l in {0..p-1}^d.
+//
+// In exact arithmetic this is the same computation (u^{AB} = M f^{AB}, and M
+// is invertible), but every operator becomes well conditioned:
+//  * the field of (A', B_c) inside A' is a polynomial of degree p-1 (per
+//    axis) in Z = exp(2 pi i xi rho / q) that takes the values w^{A'B_c} at
+//    the p check nodes Z_k = exp(2 pi i rho k / q^2); evaluating it at the
+//    check points of A = child t of A' is Lagrange interpolation, so the
+//    translation of eq. (E1) followed by M^{-1} of eq. (M1) is, per axis,
+//        U_{s,t}[l][l'] = e^{i pi rho t s} e^{i pi rho l s / q} L_t[l][l'],
+//        L_t[l][l'] = ell_{l'}( exp(i pi rho (t q + l) / q^2) ),
+//    times the scalar exp(2 pi i rho i_{A'} s) (1 when rho = 1);
+//  * the leaf state (step 2) is sum_j exp(2 pi i l . k'_j / q) f_j with the
+//    local offset k' = k - rho i_B, so no phase argument exceeds 2 pi d;
+//  * evaluation (step 4) is barycentric interpolation of w^{AB_0} at the
+//    local offset x' = x - rho i_A.
+// No inverse of the Vandermonde matrix G (cond ~ 3e8 at p = 9) is formed.
+//
+// The sweep of one level is a streaming pass: for a parent a' of T_X and a
+// tile of boxes b of T_K, the children of b are contiguous in the input row
+// a' (Morton order), and the outputs are rows a = children of a'.
+#include "bfsft_impl.h"
+
+#include <type_traits>
+
+namespace bfsft {
+
+namespace {
+
+template <typename T> struct CV;
+template <> struct CV<double> { using t = double2; };
+template <> struct CV<float> { using t = float2; };
+
+// Read-only operator tables are addressed through the constant address space:
+// wave-uniform loads from it become scalar loads, so table entries arrive in
+// SGPRs and feed the FMAs directly.
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+// complex entry i of a constant-address-space table of interleaved scalars
+template <typename Cv, typename T> __device__ __forceinline__ Cv ldc(cptr<T> p, int i)
+{
+    Cv r;
+    r.x = p[2 * i];
+    r.y = p[2 * i + 1];
+    return r;
+}
+
+template <typename V> __device__ __forceinline__ V cmul(V a, V b)
+{
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+template <typename V> __device__ __forceinline__ void cfma(V &acc, const V a, const V b)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
+template <typename V> __device__ __forceinline__ V czero()
+{
+    V r;
+    r.x = 0;
+    r.y = 0;
+    return r;
+}
+
+template <typename D, typename Sv> __device__ __forceinline__ D cvt(const Sv s)
+{
+    D r;
+    r.x = s.x;
+    r.y = s.y;
+    return r;
+}
+
+// exp(2 pi i num / den) with the numerator reduced exactly (den > 0)
+__device__ double2 expi_ratio(int64_t num, int64_t den)
+{
+    int64_t r = num % den;
+    if (r < 0) r += den;
+    double s, c;
+    sincospi(2.0 * (double)r / (double)den, &s, &c);
+    return make_double2(c, s);
+}
+
+__device__ double2 dmul(double2 a, double2 b) { return cmul(a, b); }
+
+__device__ double2 ddiv(double2 a, double2 b)
+{
+    const double den = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+// exp(2 pi i a) - exp(2 pi i b) = 2 i sin(pi (a - b)) exp(i pi (a + b)), for
+// a - b and a + b given in turns: no cancellation between close points
+__device__ double2 diff_unit(double amb, double apb)
+{
+    double s, c;
+    sincospi(apb, &s, &c);
+    const double sn = 2.0 * sinpi(amb);
+    return make_double2(-sn * s, sn * c);
+}
+
+// ---------------------------------------------------------------- tables --
+
+// One thread block, FP64.  rho = N / 2^L; all turns are exact rationals
+// N n / (2 q^2 2^L) rounded once.
+__global__ void k_tables(int p, int64_t N, int L, double2 *L64, float2 *L32, double2 *PH64,
+                         float2 *PH32, double2 *nodes, double2 *bary, double *node_turns)
+{
+    const int q = p - 1;
+    const double den = ldexp(2.0 * q * q, L);  // 2 q^2 2^L
+    __shared__ double2 lam[16];
+    const int tid = threadIdx.x;
+    if (tid < p) {
+        // barycentric weight of node k: 1 / prod_{j != k} (Z_k - Z_j), Z_k at 2k/(2q^2) rho turns
+        const int k = tid;
+        double2 prod = make_double2(1.0, 0.0);
+        for (int j = 0; j < p; ++j) {
+            if (j == k) continue;
+            const double amb = (double)(N * (int64_t)(2 * (k - j))) / den;
+            const double apb = (double)(N * (int64_t)(2 * (k + j))) / den;
+            prod = dmul(prod, diff_unit(amb, apb));
+        }
+        lam[k] = ddiv(make_double2(1.0, 0.0), prod);
+        bary[k] = lam[k];
+        nodes[k] = expi_ratio(N * (int64_t)(2 * k), (int64_t)(2 * q * q) << L);
+        node_turns[k] = (double)(N * (int64_t)k) / ldexp((double)(q * q), L);
+    }
+    __syncthreads();
+    if (tid < 2 * p) {
+        const int t = tid / p, l = tid % p;
+        const int num = t * q + l;  // point exp(i pi rho num / q^2)
+        double2 w[16];
+        double2 sum = make_double2(0.0, 0.0);
+        int exact = -1;
+        for (int k = 0; k < p; ++k) {
+            if (num == 2 * k) exact = k;
+            const double amb = (double)(N * (int64_t)(num - 2 * k)) / den;
+            const double apb = (double)(N * (int64_t)(num + 2 * k)) / den;
+            w[k] = ddiv(lam[k], diff_unit(amb, apb));
+            sum.x += w[k].x;
+            sum.y += w[k].y;
+        }
+        for (int k = 0; k < p; ++k) {
+            double2 v;
+            if (exact >= 0)
+                v = make_double2(k == exact ? 1.0 : 0.0, 0.0);
+            else
+                v = ddiv(w[k], sum);
+            L64[(t * p + l) * p + k] = v;
+            L32[(t * p + l) * p + k] = make_float2((float)v.x, (float)v.y);
+        }
+        // phase of the child at offset s = 1: exp(i pi rho (t q + l) / q)
+        const double2 ph = expi_ratio(N * (int64_t)num, (int64_t)(2 * q) << L);
+        PH64[t * p + l] = ph;
+        PH32[t * p + l] = make_float2((float)ph.x, (float)ph.y);
+    }
+}
+
+__global__ void k_sigma(const uint64_t *__restrict__ keys, int64_t n, int d, int m, int L,
+                        int64_t N, double2 *__restrict__ sig)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = keys[i];
+    for (int a = 0; a < d; ++a) {
+        int64_t c = 0;
+        for (int b = 0; b < m; ++b) c |= (int64_t)((key >> (b * d + a)) & 1ull) << b;
+        // exp(2 pi i rho c) with rho c = N c / 2^L
+        sig[i * d + a] = expi_ratio(N * c, (int64_t)1 << L);
+    }
+}
+
+// ------------------------------------------------------------------ leaf --
+
+// Step 2: w^{A0 B}_l = sum_{k_j in B} exp(2 pi i l . k'_j / q) f_j for every
+// leaf B of T_K (A0 = root of T_X).  One thread per (leaf, grid point).
+template <int D, typename S>
+__global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
+                                             const double2 *__restrict__ f,
+                                             const int32_t *__restrict__ perm,
+                                             const int32_t *__restrict__ beg,
+                                             const double *__restrict__ local,
+                                             typename CV<S>::t *__restrict__ state)
+{
+    int PD = p;
+    for (int a = 1; a < D; ++a) PD *= p;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nleaf * PD) return;
+    const int64_t b = gid / PD;
+    const int e = (int)(gid - b * PD);
+    int lidx[3] = {0, 0, 0};
+    {
+        int r = e;
+        for (int a = D - 1; a >= 0; --a) {
+            lidx[a] = r % p;
+            r /= p;
+        }
+    }
+    const double invq = 1.0 / (double)(p - 1);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = beg[b]; t < beg[b + 1]; ++t) {
+        const int j = perm[t];
+        double turns = 0.0;
+        for (int a = 0; a < D; ++a) turns = fma((double)lidx[a], local[(int64_t)j * D + a], turns);
+        double s, c;
+        sincospi(2.0 * turns * invq, &s, &c);
+        const double2 fj = f[j];
+        acc.x += c * fj.x - s * fj.y;
+        acc.y += c * fj.y + s * fj.x;
+    }
+    typename CV<S>::t o;
+    o.x = (S)acc.x;
+    o.y = (S)acc.y;
+    state[gid] = o;
+}
+
+// ----------------------------------------------------------------- final --
+
+// Step 4: u_i = sum_l prod_a ell_{l_a}(exp(2 pi i x'_{i,a} / q)) w^{A B0}_l for
+// x_i in leaf A of T_X (barycentric Lagrange interpolation).
+template <int D, int P, typename S>
+__global__ __launch_bounds__(256) void k_final(int64_t nx, const typename CV<S>::t *__restrict__ state,
+                                              const int32_t *__restrict__ leaf_of,
+                                              const double *__restrict__ local,
+                                              const double2 *__restrict__ bary,
+                                              const double *__restrict__ node_turns,
+                                              double2 *__restrict__ u)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx) return;
+    constexpr int q = P - 1;
+    double2 ell[D][P];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double xt = local[i * D + a] / (double)q;  // turns of z = exp(2 pi i x'/q)
+        int exact = -1;
+        double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double amb = xt - node_turns[k];
+            if (amb == 0.0) exact = k;
+            const double2 w = ddiv(bary[k], diff_unit(amb, xt + node_turns[k]));
+            ell[a][k] = w;
+            sum.x += w.x;
+            sum.y += w.y;
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            ell[a][k] = exact >= 0 ? make_double2(k == exact ? 1.0 : 0.0, 0.0) : ddiv(ell[a][k], sum);
+    }
+    constexpr int PD = (D == 2) ? P * P : P * P * P;
+    const typename CV<S>::t *w = state + (int64_t)leaf_of[i] * PD;
+    double2 acc = make_double2(0.0, 0.0);
+    if (D == 2) {
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            double2 r = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int m = 0; m < P; ++m) cfma(r, ell[1][m], cvt<double2>(w[l * P + m]));
+            cfma(acc, ell[0][l], r);
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            double2 r1 = make_double2(0.0, 0.0);
+            for (int m = 0; m < P; ++m) {
+                double2 r2 = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int n = 0; n < P; ++n) cfma(r2, ell[D - 1][n], cvt<double2>(w[(l * P + m) * P + n]));
+                cfma(r1, ell[1][m], r2);
+            }
+            cfma(acc, ell[0][l], r1);
+        }
+    }
+    u[i] = acc;
+}
+
+// ------------------------------------------------------------- translate --
+
+struct TArgs {
+    const void *in;
+    void *out;
+    int64_t in_row, out_row;
+    const int32_t *x_cb;
+    const uint64_t *x_keys;
+    const int32_t *k_cb;
+    const uint64_t *k_keys;
+    const int2 *tiles;
+    int ntile;
+    const double2 *sig;
+    const void *Lt;  // [2][P][P] complex, compute precision
+    const void *PH;  // [2][P] complex, compute precision
+};
+
+constexpr int kTT = 256;  // threads of a translation work-group
+
+// Step 3, 2D.  Work-group = (a' of T_X level L-l-1, tile of T_K level l boxes).
+//   stage 1 (axis 2):  Y_j[l][m] = f2(s2_j, t2, m) sum_m' L_t2[m][m'] X_j[l][m']
+//   stage 2 (axis 1):  out_a[b][l][m] = sum_s1 f1(s1, t1, l)
+//                          sum_l' L_t1[l][l'] (sum_{j child of b, s1_j = s1} Y_j[l'][m])
+// with f(s, t, l) = 1 for s = 0 and sigma_{A'} PH_t[l] for s = 1.  The
+// operator of each stage depends only on the output child position t, so it
+// is uniform across the work-group.
+template <int P, typename S, typename C>
+__global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
+{
+    using Sv = typename CV<S>::t;
+    using Cv = typename CV<C>::t;
+    constexpr int PP = P * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Cv *Y = reinterpret_cast<Cv *>(smem);
+
+    const int64_t gid = blockIdx.x;
+    const int64_t ap = gid / a.ntile;
+    const int tile = (int)(gid - ap * a.ntile);
+    const int2 bt = a.tiles[tile];
+    const int b0 = bt.x, nb = bt.y - bt.x;
+    const int J0 = a.k_cb[b0];
+    const int nin = a.k_cb[bt.y] - J0;
+    const int A0 = a.x_cb[ap], A1 = a.x_cb[ap + 1];
+
+    Cv sig[2];
+    sig[0].x = 1; sig[0].y = 0;
+    sig[1] = sig[0];
+    if (a.sig) {
+        sig[0] = cvt<Cv>(a.sig[ap * 2 + 0]);
+        sig[1] = cvt<Cv>(a.sig[ap * 2 + 1]);
+    }
+    const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((int64_t)ap * a.in_row + J0) * PP;
+    const cptr<C> Lt = (cptr<C>)(a.Lt);
+    const cptr<C> PH = (cptr<C>)(a.PH);
+
+    for (int t2 = 0; t2 < 2; ++t2) {
+        int nout = 0;
+        for (int i = A0; i < A1; ++i) nout += (int)((a.x_keys[i] >> 1) & 1) == t2;
+        if (nout == 0) continue;
+
+        // stage 1: one thread per input row (j, l)
+        for (int v = threadIdx.x; v < nin * P; v += kTT) {
+            const int j = v / P, l = v - j * P;
+            const bool s2 = (a.k_keys[J0 + j] >> 1) & 1;
+            Cv x[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(in[j * PP + l * P + m]);
+            const Cv sg = sig[1];
+            // rolled: one table row (P scalars) is live per iteration
+#pragma unroll 1
+            for (int m = 0; m < P; ++m) {
+                Cv y = czero<Cv>();
+#pragma unroll
+                for (int mp = 0; mp < P; ++mp) cfma(y, ldc<Cv>(Lt, t2 * PP + m * P + mp), x[mp]);
+                if (s2) y = cmul(y, cmul(sg, ldc<Cv>(PH, t2 * P + m)));
+                Y[j * PP + l * P + m] = y;
+            }
+        }
+        __syncthreads();
+
+        // stage 2: one thread per output column (b, m); loop over the
+        // outputs a with this t2 (uniform), column sums shared between them
+        for (int v = threadIdx.x; v < nb * P; v += kTT) {
+            const int bl = v / P, m = v - bl * P;
+            const int jb = a.k_cb[b0 + bl] - J0, je = a.k_cb[b0 + bl + 1] - J0;
+            Cv z[2][P];
+            bool has[2] = {false, false};
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+                for (int l = 0; l < P; ++l) z[s1][l] = czero<Cv>();
+            for (int j = jb; j < je; ++j) {
+                const int s1 = (int)(a.k_keys[J0 + j] & 1);
+                has[s1] = true;
+                if (s1) {
+#pragma unroll
+                    for (int l = 0; l < P; ++l) {
+                        const Cv yv = Y[j * PP + l * P + m];
+                        z[1][l].x += yv.x;
+                        z[1][l].y += yv.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int l = 0; l < P; ++l) {
+                        const Cv yv = Y[j * PP + l * P + m];
+                        z[0][l].x += yv.x;
+                        z[0][l].y += yv.y;
+                    }
+                }
+            }
+            for (int i = A0; i < A1; ++i) {
+                const int t = (int)(a.x_keys[i] & 3);
+                if ((t >> 1) != t2) continue;
+                const int t1 = t & 1;
+                Sv *out = reinterpret_cast<Sv *>(a.out) + ((int64_t)i * a.out_row + b0 + bl) * PP;
+                const Cv sg = sig[0];
+#pragma unroll 1
+                for (int l = 0; l < P; ++l) {
+                    Cv r0 = czero<Cv>(), r1 = czero<Cv>();
+#pragma unroll
+                    for (int lp = 0; lp < P; ++lp) {
+                        const Cv lv = ldc<Cv>(Lt, t1 * PP + l * P + lp);
+                        cfma(r0, lv, z[0][lp]);
+                        cfma(r1, lv, z[1][lp]);
+                    }
+                    Cv o = r0;
+                    if (has[1]) {
+                        const Cv r1p = cmul(r1, cmul(sg, ldc<Cv>(PH, t1 * P + l)));
+                        o.x += r1p.x;
+                        o.y += r1p.y;
+                    }
+                    Sv so;
+                    so.x = (S)o.x;
+                    so.y = (S)o.y;
+                    out[l * P + m] = so;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- export --
+
+// Parity probe: pot[a][b][l] = exp(2 pi i x^A_l . c^B / N) w^{AB}_l, i.e. the
+// paper's check potential u^{AB} at T_K level lvl; the phase is
+// sum_a rho i_B (q i_A + l_a) / q with the numerator reduced exactly.
+template <typename S>
+__global__ void k_export(int d, int p, const typename CV<S>::t *__restrict__ st,
+                         const uint64_t *__restrict__ xkeys, int64_t nA,
+                         const uint64_t *__restrict__ kkeys, int64_t nB, int lvl, int L,
+                         int64_t N, double2 *__restrict__ pot)
+{
+    int PD = p;
+    for (int a = 1; a < d; ++a) PD *= p;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nA * nB * PD) return;
+    const int64_t ab = gid / PD;
+    const int e = (int)(gid - ab * PD);
+    const int64_t ia = ab / nB, ib = ab - ia * nB;
+    const int q = p - 1;
+    const uint64_t D = (uint64_t)q << L;
+    const uint64_t Nm = (uint64_t)N % D;
+    const int mA = L - lvl;
+    uint64_t tot = 0;
+    int r = e;
+    int lix[3];
+    for (int a = d - 1; a >= 0; --a) {
+        lix[a] = r % p;
+        r /= p;
+    }
+    for (int a = 0; a < d; ++a) {
+        uint64_t cA = 0, cB = 0;
+        for (int b = 0; b < mA; ++b) cA |= ((xkeys[ia] >> (b * d + a)) & 1ull) << b;
+        for (int b = 0; b < lvl; ++b) cB |= ((kkeys[ib] >> (b * d + a)) & 1ull) << b;
+        const uint64_t n = (cB * ((uint64_t)q * cA + (uint64_t)lix[a])) % D;
+        tot = (tot + (Nm * n) % D) % D;
+    }
+    double s, c;
+    sincospi(2.0 * (double)tot / (double)D, &s, &c);
+    const double2 w = cvt<double2>(st[gid]);
+    pot[gid] = make_double2(c * w.x - s * w.y, c * w.y + s * w.x);
+}
+
+__global__ void k_zero_c128(double2 *u, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = make_double2(0.0, 0.0);
+}
+
+inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+template <int P> struct PTag { static constexpr int value = P; };
+
+template <typename F> void dispatch_p2(int p, F &&f)
+{
+    switch (p) {
+    case 3: f(PTag<3>{}); break;
+    case 4: f(PTag<4>{}); break;
+    case 5: f(PTag<5>{}); break;
+    case 6: f(PTag<6>{}); break;
+    case 7: f(PTag<7>{}); break;
+    case 8: f(PTag<8>{}); break;
+    case 9: f(PTag<9>{}); break;
+    case 10: f(PTag<10>{}); break;
+    case 11: f(PTag<11>{}); break;
+    case 12: f(PTag<12>{}); break;
+    default: throw Error{BFSFT_EINVAL, "unsupported p"};
+    }
+}
+
+template <typename F> void dispatch_prec(int precision, F &&f)
+{
+    switch (precision) {
+    case BFSFT_FP64: f((double *)nullptr, (double *)nullptr); break;
+    case BFSFT_MIXED: f((float *)nullptr, (double *)nullptr); break;
+    case BFSFT_FP32: f((float *)nullptr, (float *)nullptr); break;
+    default: throw Error{BFSFT_EINVAL, "unsupported precision"};
+    }
+}
+
+constexpr int kLdsBudget = 40 * 1024;
+
+}  // namespace
+
+void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t s)
+{
+    tb.L64 = (double *)arena.alloc(sizeof(double2) * 2 * p * p);
+    tb.L32 = (float *)arena.alloc(sizeof(float2) * 2 * p * p);
+    tb.PH64 = (double *)arena.alloc(sizeof(double2) * 2 * p);
+    tb.PH32 = (float *)arena.alloc(sizeof(float2) * 2 * p);
+    tb.nodes = (double *)arena.alloc(sizeof(double2) * p);
+    tb.bary = (double *)arena.alloc(sizeof(double2) * p);
+    tb.node_turns = (double *)arena.alloc(sizeof(double) * p);
+    k_tables<<<1, 64, 0, s>>>(p, N, L, (double2 *)tb.L64, (float2 *)tb.L32, (double2 *)tb.PH64,
+                              (float2 *)tb.PH32, (double2 *)tb.nodes, (double2 *)tb.bary,
+                              tb.node_turns);
+    BF_HIP(hipGetLastError());
+}
+
+int translate_max_inputs(int d, int p, int precision)
+{
+    const int csize = precision == BFSFT_FP32 ? 8 : 16;
+    int PD = p;
+    for (int a = 1; a < d; ++a) PD *= p;
+    int m = kLdsBudget / (PD * csize);
+    const int lanes = kTT / p;  // one input row per thread in stage 1
+    if (m > lanes) m = lanes;
+    if (m < (1 << d)) m = 1 << d;
+    return m;
+}
+
+void launch_translate(const Launch &c, const LevelArgs &la)
+{
+    if (la.nap == 0 || la.ntile == 0) return;
+    if (c.d != 2) throw Error{BFSFT_EINVAL, "3D translation not built"};
+    TArgs a;
+    a.in = la.in;
+    a.out = la.out;
+    a.in_row = la.in_row;
+    a.out_row = la.out_row;
+    a.x_cb = la.x_cb;
+    a.x_keys = la.x_keys;
+    a.k_cb = la.k_cb;
+    a.k_keys = la.k_keys;
+    a.tiles = la.tiles;
+    a.ntile = la.ntile;
+    a.sig = reinterpret_cast<const double2 *>(la.sig);
+    const bool f32 = c.precision == BFSFT_FP32;
+    a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
+    a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
+    const int maxin = translate_max_inputs(c.d, c.p, c.precision);
+    const int64_t grid = la.nap * la.ntile;
+    dispatch_p2(c.p, [&](auto tag) {
+        constexpr int P = decltype(tag)::value;
+        dispatch_prec(c.precision, [&](auto *sp, auto *cp) {
+            using S = std::remove_pointer_t<decltype(sp)>;
+            using C = std::remove_pointer_t<decltype(cp)>;
+            const size_t lds = (size_t)maxin * P * P * sizeof(typename CV<C>::t);
+            k_translate2d<P, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+        });
+    });
+    BF_HIP(hipGetLastError());
+}
+
+void launch_leaf(const Launch &c, const double *f, const Tree &tk, double, void *state)
+{
+    const int64_t nl = tk.count[tk.L];
+    int PD = c.p;
+    for (int a = 1; a < c.d; ++a) PD *= c.p;
+    const int64_t n = nl * PD;
+    if (n == 0) return;
+    const bool f32 = c.precision != BFSFT_FP64;
+    if (c.d == 2) {
+        if (f32)
+            k_leaf<2, float><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
+                                                               tk.leaf_beg, tk.local, (float2 *)state);
+        else
+            k_leaf<2, double><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
+                                                                tk.leaf_beg, tk.local, (double2 *)state);
+    } else {
+        if (f32)
+            k_leaf<3, float><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
+                                                               tk.leaf_beg, tk.local, (float2 *)state);
+        else
+            k_leaf<3, double><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
+                                                                tk.leaf_beg, tk.local, (double2 *)state);
+    }
+    BF_HIP(hipGetLastError());
+}
+
+void launch_final(const Launch &c, const void *state, const Tree &tx, double, int64_t nx, double *u)
+{
+    if (nx == 0) return;
+    const bool f32 = c.precision != BFSFT_FP64;
+    dispatch_p2(c.p, [&](auto tag) {
+        constexpr int P = decltype(tag)::value;
+        if (c.d == 2) {
+            if (f32)
+                k_final<2, P, float><<<nblk(nx, 256), 256, 0, c.stream>>>(
+                    nx, (const float2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
+                    c.tb->node_turns, (double2 *)u);
+            else
+                k_final<2, P, double><<<nblk(nx, 256), 256, 0, c.stream>>>(
+                    nx, (const double2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
+                    c.tb->node_turns, (double2 *)u);
+        } else if constexpr (P <= 8) {
+            if (f32)
+                k_final<3, P, float><<<nblk(nx, 256), 256, 0, c.stream>>>(
+                    nx, (const float2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
+                    c.tb->node_turns, (double2 *)u);
+            else
+                k_final<3, P, double><<<nblk(nx, 256), 256, 0, c.stream>>>(
+                    nx, (const double2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
+                    c.tb->node_turns, (double2 *)u);
+        } else {
+            throw Error{BFSFT_EINVAL, "p > 8 in 3D"};
+        }
+    });
+    BF_HIP(hipGetLastError());
+}
+
+void launch_export(const Launch &c, const void *state, const uint64_t *xkeys, int64_t nA,
+                   const uint64_t *kkeys, int64_t nB, int lvl, int L, int64_t N, double *pot)
+{
+    int PD = c.p;
+    for (int a = 1; a < c.d; ++a) PD *= c.p;
+    const int64_t n = nA * nB * PD;
+    if (n == 0) return;
+    if (c.precision == BFSFT_FP64)
+        k_export<double><<<nblk(n, 256), 256, 0, c.stream>>>(c.d, c.p, (const double2 *)state, xkeys,
+                                                            nA, kkeys, nB, lvl, L, N, (double2 *)pot);
+    else
+        k_export<float><<<nblk(n, 256), 256, 0, c.stream>>>(c.d, c.p, (const float2 *)state, xkeys,
+                                                           nA, kkeys, nB, lvl, L, N, (double2 *)pot);
+    BF_HIP(hipGetLastError());
+}
+
+void launch_zero_c128(double *u, int64_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    k_zero_c128<<<nblk(n, 256), 256, 0, s>>>((double2 *)u, n);
+    BF_HIP(hipGetLastError());
+}
+
+void launch_sigma(const uint64_t *keys, int64_t n, int d, int m, int L, int64_t N, double *sig,
+                  hipStream_t s)
+{
+    if (n == 0) return;
+    k_sigma<<<nblk(n, 256), 256, 0, s>>>(keys, n, d, m, L, N, (double2 *)sig);
+    BF_HIP(hipGetLastError());
+}
+
+}  // namespace bfsft
