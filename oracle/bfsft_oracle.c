@@ -13,7 +13,7 @@
  *                       exp(2 pi i x_i.k_j / N) f_j, in FP64, with the phase
  *                       x_i.k_j / N reduced modulo 1 in double-double.
  *   O2  or_bf_*       - the butterfly algorithm of Section 2.2 (steps 1-4),
- *                       f-form (equivalent charges), FP64, in the paper's
+ *                       f-form (equivalent charges), in the paper's
  *                       order: check potentials u^{AB} are evaluated from the
  *                       children's charges with E = E1 (x) E2 (Section 2.1,
  *                       eq. E1), then f^{AB} = M^{-1} u^{AB} with
@@ -23,7 +23,11 @@
  *                       phase is an integer multiple of rho/(q 2^k), reduced
  *                       modulo 1 in 128-bit integers before one sin/cos.
  *                       G^{-1} is applied by an LU solve with partial
- *                       pivoting (backward stable).
+ *                       pivoting.  The butterfly's arithmetic (phases,
+ *                       solves, products, sums) is x87 long double: in the
+ *                       f-form the charges inherit the conditioning of G
+ *                       (about 3e8 at p = 9, 5e11 at p = 11, 1e13 at p = 12)
+ *                       and FP64 loses field accuracy from p = 11 on.
  *
  * Readings where the paper is silent (they are shared with the GPU library by
  * specification, not by code):
@@ -46,7 +50,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-typedef double complex cplx;
+typedef long double complex cplx;   /* butterfly (O2) */
+typedef double complex dcplx;       /* direct sum (O1) */
 typedef unsigned __int128 u128;
 
 #define OR_PMAX 16
@@ -56,7 +61,16 @@ typedef unsigned __int128 u128;
 /* ------------------------------------------------------------------------- */
 
 /* exp(2 pi i t) for t given in turns */
-static cplx expi_turns(double t)
+static cplx expi_turns(long double t)
+{
+    t -= nearbyintl(t);
+    long double s, c;
+    sincosl(2.0L * M_PIl * t, &s, &c);
+    return CMPLXL(c, s);
+}
+
+/* the same in FP64, for the direct sum */
+static dcplx expi_turns_d(double t)
 {
     t -= nearbyint(t);
     double s, c;
@@ -71,7 +85,7 @@ static cplx expi_rational(uint64_t a, uint64_t b, int64_t N, int L)
     u128 num = (u128)a * (u128)(uint64_t)N;
     u128 den = (u128)b << L;
     u128 r = num % den;
-    return expi_turns((double)(uint64_t)r / (double)(uint64_t)den);
+    return expi_turns((long double)(uint64_t)r / (long double)(uint64_t)den);
 }
 
 /* double-double helpers for O1 and for phases of arbitrary coordinates */
@@ -109,8 +123,13 @@ static inline dd_t dd_div(dd_t a, double b)
 static cplx expi_dd(dd_t t)
 {
     double n = nearbyint(t.hi);
-    double r = (t.hi - n) + t.lo;
-    return expi_turns(r);
+    return expi_turns((long double)(t.hi - n) + (long double)t.lo);
+}
+
+static dcplx expi_dd_d(dd_t t)
+{
+    double n = nearbyint(t.hi);
+    return expi_turns_d((t.hi - n) + t.lo);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -123,18 +142,18 @@ void or_direct(int d, double N, const double *x, const double *k,
                const double *f, int64_t nk, const int64_t *idx, int64_t ns,
                double *u)
 {
-    const cplx *fc = (const cplx *)f;
-    cplx *uc = (cplx *)u;
+    const dcplx *fc = (const dcplx *)f;
+    dcplx *uc = (dcplx *)u;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t s = 0; s < ns; ++s) {
         const double *xi = x + idx[s] * d;
-        cplx acc = 0;
+        dcplx acc = 0;
         for (int64_t j = 0; j < nk; ++j) {
             const double *kj = k + j * d;
             dd_t t = two_prod(xi[0], kj[0]);
             for (int a = 1; a < d; ++a)
                 t = dd_add(t, two_prod(xi[a], kj[a]));
-            acc += expi_dd(dd_div(t, N)) * fc[j];
+            acc += expi_dd_d(dd_div(t, N)) * fc[j];
         }
         uc[s] = acc;
     }
@@ -304,9 +323,9 @@ static void lu_factor(cplx *A, int *piv, int p)
 {
     for (int c = 0; c < p; ++c) {
         int r = c;
-        double best = cabs(A[c * p + c]);
+        long double best = cabsl(A[c * p + c]);
         for (int i = c + 1; i < p; ++i)
-            if (cabs(A[i * p + c]) > best) { best = cabs(A[i * p + c]); r = i; }
+            if (cabsl(A[i * p + c]) > best) { best = cabsl(A[i * p + c]); r = i; }
         piv[c] = r;
         if (r != c)
             for (int j = 0; j < p; ++j) { cplx t = A[c * p + j]; A[c * p + j] = A[r * p + j]; A[r * p + j] = t; }
@@ -471,9 +490,9 @@ void or_bf_matrix_M(void *h, int64_t iA, int64_t iB, double *out)
     or_plan *P = h;
     cplx m11[OR_PMAX], m12[OR_PMAX];
     m_diagonals(P, iA, iB, m11, m12);
-    cplx *o = (cplx *)out;
+    dcplx *o = (dcplx *)out;
     for (int l = 0; l < P->p; ++l)
-        for (int m = 0; m < P->p; ++m) o[l * P->p + m] = m11[l] * P->G[l * P->p + m] * m12[m];
+        for (int m = 0; m < P->p; ++m) o[l * P->p + m] = (dcplx)(m11[l] * P->G[l * P->p + m] * m12[m]);
 }
 
 void or_bf_matrix_E(void *h, int64_t iA, int64_t ic, double *out)
@@ -481,9 +500,9 @@ void or_bf_matrix_E(void *h, int64_t iA, int64_t ic, double *out)
     or_plan *P = h;
     cplx e11[OR_PMAX], e12[OR_PMAX];
     e_diagonals(P, iA, ic, e11, e12);
-    cplx *o = (cplx *)out;
+    dcplx *o = (dcplx *)out;
     for (int l = 0; l < P->p; ++l)
-        for (int m = 0; m < P->p; ++m) o[l * P->p + m] = e11[l] * P->H[l * P->p + m] * e12[m];
+        for (int m = 0; m < P->p; ++m) o[l * P->p + m] = (dcplx)(e11[l] * P->H[l * P->p + m] * e12[m]);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -504,8 +523,9 @@ int or_bf_run(void *h, const double *f_in, double *u_out, int dump_level,
     const int d = P->d, p = P->p, q = P->q, L = P->L;
     int PD = 1;
     for (int a = 0; a < d; ++a) PD *= p;
-    const cplx *f = (const cplx *)f_in;
-    cplx *u = (cplx *)u_out;
+    const dcplx *f = (const dcplx *)f_in;
+    dcplx *u = (dcplx *)u_out;
+    dcplx *du = (dcplx *)dump_u, *df = (dcplx *)dump_f;
 
     for (int64_t i = 0; i < P->nx; ++i) u[i] = 0;
     if (P->nx == 0 || P->nk == 0) return 0;
@@ -535,10 +555,12 @@ int or_bf_run(void *h, const double *f_in, double *u_out, int dump_level,
                 X[e] += w;
             }
         }
-        if (dump_level == L && dump_u) memcpy((cplx *)dump_u + b * PD, X, sizeof(cplx) * PD);
+        if (dump_level == L && du)
+            for (int e = 0; e < PD; ++e) du[b * PD + e] = (dcplx)X[e];
         int64_t iA[3] = {0, 0, 0};
         solve_matching(P, iA, iB, X);
-        if (dump_level == L && dump_f) memcpy((cplx *)dump_f + b * PD, X, sizeof(cplx) * PD);
+        if (dump_level == L && df)
+            for (int e = 0; e < PD; ++e) df[b * PD + e] = (dcplx)X[e];
     }
 
     /* step 3: for l = L-1 .. 0, every B at T_K level l and every A at T_X
@@ -577,9 +599,11 @@ int or_bf_run(void *h, const double *f_in, double *u_out, int dump_level,
                 }
                 for (int e = 0; e < PD; ++e) U[e] += Y[e];
             }
-            if (dump_level == lvl && dump_u) memcpy((cplx *)dump_u + ab * PD, U, sizeof(cplx) * PD);
+            if (dump_level == lvl && du)
+                for (int e = 0; e < PD; ++e) du[ab * PD + e] = (dcplx)U[e];
             solve_matching(P, iA, iB, U);
-            if (dump_level == lvl && dump_f) memcpy((cplx *)dump_f + ab * PD, U, sizeof(cplx) * PD);
+            if (dump_level == lvl && df)
+                for (int e = 0; e < PD; ++e) df[ab * PD + e] = (dcplx)U[e];
         }
         free(cur);
         cur = nxt;
@@ -606,7 +630,7 @@ int or_bf_run(void *h, const double *f_in, double *u_out, int dump_level,
                 for (int s = d - 1; s >= 0; --s) { w *= ph[s][r % p]; r /= p; }
                 acc += w;
             }
-            u[i] = acc;
+            u[i] = (dcplx)acc;
         }
     }
     free(cur);
