@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 GATE = 1e-6
 COUNTERS = os.path.join(ROOT, "profiles", "translate_c2_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0801_1524_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_0801_1524_amd", "csrc", "translate.hip")
 
 
 def log(*a):
@@ -123,7 +123,7 @@ def cpu_baseline_leg(P, gpu_results, S):
     t_bf = time.perf_counter() - t
     log(f"[bench] oracle butterfly {t_bf:.2f} s")
     base = {"value": round(P.nx / t_bf, 1), "unit": "outputs/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full transform of the same workload ({P.nx} outputs), FP64 f-form butterfly",
+            "sample": f"one full transform of the same workload ({P.nx} outputs), f-form butterfly (long double)",
             "seconds": round(t_bf, 3),
             "direct_sum_est_seconds": round(t_direct * P.nx / len(S), 2)}
     return base, errs
@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precisions", default="mixed,fp64,fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--calib", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
@@ -145,6 +147,14 @@ def main():
     import torch
     import paper_0801_1524_amd as bf
     from paper_0801_1524_amd import synth
+
+    if args.calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration copy: 1073741824 bytes read, 1073741824 bytes written")
 
     P = synth.config("c2")
     S = synth.error_subset(P.nx, 2)

@@ -59,6 +59,7 @@ struct bfsft_plan {
     Tables tb;
     std::vector<int2 *> tiles;    // per T_K level l = 0..L-1 (output level of the step)
     std::vector<int> ntile;
+    std::vector<int> nin_max;     // most children in a tile of level l
     std::vector<double *> sig;    // per T_X level m = 0..L-1 (rows a'), null when rho == 1
     void *buf[2] = {nullptr, nullptr};
     size_t state_size = 16;
@@ -155,6 +156,7 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     build_tables(P->tb, P->p, P->N, P->L, P->arena, s);
     P->tiles.assign(P->L, nullptr);
     P->ntile.assign(P->L, 0);
+    P->nin_max.assign(P->L, 0);
     P->sig.assign(P->L, nullptr);
     if (P->nx == 0 || P->nk == 0) {
         BF_HIP(hipStreamSynchronize(s));
@@ -165,8 +167,10 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     for (int l = 0; l <= P->L; ++l)
         maxpairs = std::max(maxpairs, (size_t)P->tx.count[P->L - l] * (size_t)P->tk.count[l]);
     for (int l = 0; l < P->L; ++l) {
-        std::vector<int2> t = make_tiles(P->tk.child_beg_host[l], maxin);
+        const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
+        std::vector<int2> t = make_tiles(cb, maxin);
         P->ntile[l] = (int)t.size();
+        for (const int2 &b : t) P->nin_max[l] = std::max(P->nin_max[l], cb[b.y] - cb[b.x]);
         P->tiles[l] = (int2 *)P->arena.alloc(sizeof(int2) * t.size());
         BF_HIP(hipMemcpyAsync(P->tiles[l], t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice, s));
         BF_HIP(hipStreamSynchronize(s));  // t is a host temporary
@@ -212,6 +216,7 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
         a.k_keys = P->tk.keys[l + 1];
         a.tiles = P->tiles[l];
         a.ntile = P->ntile[l];
+        a.nin_max = P->nin_max[l];
         a.nap = P->tx.count[L - l - 1];
         a.sig = P->sig[L - l - 1];
         launch_translate(c, a);

@@ -89,6 +89,7 @@ struct LevelArgs {
     const uint64_t *k_keys;  // T_K level l+1 keys (child position s)
     const int2 *tiles;       // [ntile] b ranges
     int ntile;
+    int nin_max;             // most children of any tile
     int64_t nap;             // rows a'
     const double *sig;       // [nap][d] complex exp(2 pi i rho i_{A'}) or null (rho == 1)
 };

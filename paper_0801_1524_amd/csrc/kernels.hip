@@ -28,62 +28,14 @@
 // tile of boxes b of T_K, the children of b are contiguous in the input row
 // a' (Morton order), and the outputs are rows a = children of a'.
 #include "bfsft_impl.h"
+#include "cplx.h"
+#include "dispatch.h"
 
 #include <type_traits>
 
 namespace bfsft {
 
 namespace {
-
-template <typename T> struct CV;
-template <> struct CV<double> { using t = double2; };
-template <> struct CV<float> { using t = float2; };
-
-// Read-only operator tables are addressed through the constant address space:
-// wave-uniform loads from it become scalar loads, so table entries arrive in
-// SGPRs and feed the FMAs directly.
-template <typename T> using cptr = const __attribute__((address_space(4))) T *;
-
-// complex entry i of a constant-address-space table of interleaved scalars
-template <typename Cv, typename T> __device__ __forceinline__ Cv ldc(cptr<T> p, int i)
-{
-    Cv r;
-    r.x = p[2 * i];
-    r.y = p[2 * i + 1];
-    return r;
-}
-
-template <typename V> __device__ __forceinline__ V cmul(V a, V b)
-{
-    V r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-
-template <typename V> __device__ __forceinline__ void cfma(V &acc, const V a, const V b)
-{
-    acc.x = fma(a.x, b.x, acc.x);
-    acc.x = fma(-a.y, b.y, acc.x);
-    acc.y = fma(a.x, b.y, acc.y);
-    acc.y = fma(a.y, b.x, acc.y);
-}
-
-template <typename V> __device__ __forceinline__ V czero()
-{
-    V r;
-    r.x = 0;
-    r.y = 0;
-    return r;
-}
-
-template <typename D, typename Sv> __device__ __forceinline__ D cvt(const Sv s)
-{
-    D r;
-    r.x = s.x;
-    r.y = s.y;
-    return r;
-}
 
 // exp(2 pi i num / den) with the numerator reduced exactly (den > 0)
 __device__ double2 expi_ratio(int64_t num, int64_t den)
@@ -289,148 +241,6 @@ __global__ __launch_bounds__(256) void k_final(int64_t nx, const typename CV<S>:
     u[i] = acc;
 }
 
-// ------------------------------------------------------------- translate --
-
-struct TArgs {
-    const void *in;
-    void *out;
-    int64_t in_row, out_row;
-    const int32_t *x_cb;
-    const uint64_t *x_keys;
-    const int32_t *k_cb;
-    const uint64_t *k_keys;
-    const int2 *tiles;
-    int ntile;
-    const double2 *sig;
-    const void *Lt;  // [2][P][P] complex, compute precision
-    const void *PH;  // [2][P] complex, compute precision
-};
-
-constexpr int kTT = 256;  // threads of a translation work-group
-
-// Step 3, 2D.  Work-group = (a' of T_X level L-l-1, tile of T_K level l boxes).
-//   stage 1 (axis 2):  Y_j[l][m] = f2(s2_j, t2, m) sum_m' L_t2[m][m'] X_j[l][m']
-//   stage 2 (axis 1):  out_a[b][l][m] = sum_s1 f1(s1, t1, l)
-//                          sum_l' L_t1[l][l'] (sum_{j child of b, s1_j = s1} Y_j[l'][m])
-// with f(s, t, l) = 1 for s = 0 and sigma_{A'} PH_t[l] for s = 1.  The
-// operator of each stage depends only on the output child position t, so it
-// is uniform across the work-group.
-template <int P, typename S, typename C>
-__global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
-{
-    using Sv = typename CV<S>::t;
-    using Cv = typename CV<C>::t;
-    constexpr int PP = P * P;
-    extern __shared__ __align__(16) unsigned char smem[];
-    Cv *Y = reinterpret_cast<Cv *>(smem);
-
-    const int64_t gid = blockIdx.x;
-    const int64_t ap = gid / a.ntile;
-    const int tile = (int)(gid - ap * a.ntile);
-    const int2 bt = a.tiles[tile];
-    const int b0 = bt.x, nb = bt.y - bt.x;
-    const int J0 = a.k_cb[b0];
-    const int nin = a.k_cb[bt.y] - J0;
-    const int A0 = a.x_cb[ap], A1 = a.x_cb[ap + 1];
-
-    Cv sig[2];
-    sig[0].x = 1; sig[0].y = 0;
-    sig[1] = sig[0];
-    if (a.sig) {
-        sig[0] = cvt<Cv>(a.sig[ap * 2 + 0]);
-        sig[1] = cvt<Cv>(a.sig[ap * 2 + 1]);
-    }
-    const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((int64_t)ap * a.in_row + J0) * PP;
-    const cptr<C> Lt = (cptr<C>)(a.Lt);
-    const cptr<C> PH = (cptr<C>)(a.PH);
-
-    for (int t2 = 0; t2 < 2; ++t2) {
-        int nout = 0;
-        for (int i = A0; i < A1; ++i) nout += (int)((a.x_keys[i] >> 1) & 1) == t2;
-        if (nout == 0) continue;
-
-        // stage 1: one thread per input row (j, l)
-        for (int v = threadIdx.x; v < nin * P; v += kTT) {
-            const int j = v / P, l = v - j * P;
-            const bool s2 = (a.k_keys[J0 + j] >> 1) & 1;
-            Cv x[P];
-#pragma unroll
-            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(in[j * PP + l * P + m]);
-            const Cv sg = sig[1];
-            // rolled: one table row (P scalars) is live per iteration
-#pragma unroll 1
-            for (int m = 0; m < P; ++m) {
-                Cv y = czero<Cv>();
-#pragma unroll
-                for (int mp = 0; mp < P; ++mp) cfma(y, ldc<Cv>(Lt, t2 * PP + m * P + mp), x[mp]);
-                if (s2) y = cmul(y, cmul(sg, ldc<Cv>(PH, t2 * P + m)));
-                Y[j * PP + l * P + m] = y;
-            }
-        }
-        __syncthreads();
-
-        // stage 2: one thread per output column (b, m); loop over the
-        // outputs a with this t2 (uniform), column sums shared between them
-        for (int v = threadIdx.x; v < nb * P; v += kTT) {
-            const int bl = v / P, m = v - bl * P;
-            const int jb = a.k_cb[b0 + bl] - J0, je = a.k_cb[b0 + bl + 1] - J0;
-            Cv z[2][P];
-            bool has[2] = {false, false};
-#pragma unroll
-            for (int s1 = 0; s1 < 2; ++s1)
-#pragma unroll
-                for (int l = 0; l < P; ++l) z[s1][l] = czero<Cv>();
-            for (int j = jb; j < je; ++j) {
-                const int s1 = (int)(a.k_keys[J0 + j] & 1);
-                has[s1] = true;
-                if (s1) {
-#pragma unroll
-                    for (int l = 0; l < P; ++l) {
-                        const Cv yv = Y[j * PP + l * P + m];
-                        z[1][l].x += yv.x;
-                        z[1][l].y += yv.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int l = 0; l < P; ++l) {
-                        const Cv yv = Y[j * PP + l * P + m];
-                        z[0][l].x += yv.x;
-                        z[0][l].y += yv.y;
-                    }
-                }
-            }
-            for (int i = A0; i < A1; ++i) {
-                const int t = (int)(a.x_keys[i] & 3);
-                if ((t >> 1) != t2) continue;
-                const int t1 = t & 1;
-                Sv *out = reinterpret_cast<Sv *>(a.out) + ((int64_t)i * a.out_row + b0 + bl) * PP;
-                const Cv sg = sig[0];
-#pragma unroll 1
-                for (int l = 0; l < P; ++l) {
-                    Cv r0 = czero<Cv>(), r1 = czero<Cv>();
-#pragma unroll
-                    for (int lp = 0; lp < P; ++lp) {
-                        const Cv lv = ldc<Cv>(Lt, t1 * PP + l * P + lp);
-                        cfma(r0, lv, z[0][lp]);
-                        cfma(r1, lv, z[1][lp]);
-                    }
-                    Cv o = r0;
-                    if (has[1]) {
-                        const Cv r1p = cmul(r1, cmul(sg, ldc<Cv>(PH, t1 * P + l)));
-                        o.x += r1p.x;
-                        o.y += r1p.y;
-                    }
-                    Sv so;
-                    so.x = (S)o.x;
-                    so.y = (S)o.y;
-                    out[l * P + m] = so;
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // ----------------------------------------------------------------- export --
 
 // Parity probe: pot[a][b][l] = exp(2 pi i x^A_l . c^B / N) w^{AB}_l, i.e. the
@@ -481,37 +291,6 @@ __global__ void k_zero_c128(double2 *u, int64_t n)
 
 inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
-template <int P> struct PTag { static constexpr int value = P; };
-
-template <typename F> void dispatch_p2(int p, F &&f)
-{
-    switch (p) {
-    case 3: f(PTag<3>{}); break;
-    case 4: f(PTag<4>{}); break;
-    case 5: f(PTag<5>{}); break;
-    case 6: f(PTag<6>{}); break;
-    case 7: f(PTag<7>{}); break;
-    case 8: f(PTag<8>{}); break;
-    case 9: f(PTag<9>{}); break;
-    case 10: f(PTag<10>{}); break;
-    case 11: f(PTag<11>{}); break;
-    case 12: f(PTag<12>{}); break;
-    default: throw Error{BFSFT_EINVAL, "unsupported p"};
-    }
-}
-
-template <typename F> void dispatch_prec(int precision, F &&f)
-{
-    switch (precision) {
-    case BFSFT_FP64: f((double *)nullptr, (double *)nullptr); break;
-    case BFSFT_MIXED: f((float *)nullptr, (double *)nullptr); break;
-    case BFSFT_FP32: f((float *)nullptr, (float *)nullptr); break;
-    default: throw Error{BFSFT_EINVAL, "unsupported precision"};
-    }
-}
-
-constexpr int kLdsBudget = 40 * 1024;
-
 }  // namespace
 
 void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t s)
@@ -526,51 +305,6 @@ void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t
     k_tables<<<1, 64, 0, s>>>(p, N, L, (double2 *)tb.L64, (float2 *)tb.L32, (double2 *)tb.PH64,
                               (float2 *)tb.PH32, (double2 *)tb.nodes, (double2 *)tb.bary,
                               tb.node_turns);
-    BF_HIP(hipGetLastError());
-}
-
-int translate_max_inputs(int d, int p, int precision)
-{
-    const int csize = precision == BFSFT_FP32 ? 8 : 16;
-    int PD = p;
-    for (int a = 1; a < d; ++a) PD *= p;
-    int m = kLdsBudget / (PD * csize);
-    const int lanes = kTT / p;  // one input row per thread in stage 1
-    if (m > lanes) m = lanes;
-    if (m < (1 << d)) m = 1 << d;
-    return m;
-}
-
-void launch_translate(const Launch &c, const LevelArgs &la)
-{
-    if (la.nap == 0 || la.ntile == 0) return;
-    if (c.d != 2) throw Error{BFSFT_EINVAL, "3D translation not built"};
-    TArgs a;
-    a.in = la.in;
-    a.out = la.out;
-    a.in_row = la.in_row;
-    a.out_row = la.out_row;
-    a.x_cb = la.x_cb;
-    a.x_keys = la.x_keys;
-    a.k_cb = la.k_cb;
-    a.k_keys = la.k_keys;
-    a.tiles = la.tiles;
-    a.ntile = la.ntile;
-    a.sig = reinterpret_cast<const double2 *>(la.sig);
-    const bool f32 = c.precision == BFSFT_FP32;
-    a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
-    a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
-    const int maxin = translate_max_inputs(c.d, c.p, c.precision);
-    const int64_t grid = la.nap * la.ntile;
-    dispatch_p2(c.p, [&](auto tag) {
-        constexpr int P = decltype(tag)::value;
-        dispatch_prec(c.precision, [&](auto *sp, auto *cp) {
-            using S = std::remove_pointer_t<decltype(sp)>;
-            using C = std::remove_pointer_t<decltype(cp)>;
-            const size_t lds = (size_t)maxin * P * P * sizeof(typename CV<C>::t);
-            k_translate2d<P, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
-        });
-    });
     BF_HIP(hipGetLastError());
 }
 
@@ -604,7 +338,7 @@ void launch_final(const Launch &c, const void *state, const Tree &tx, double, in
 {
     if (nx == 0) return;
     const bool f32 = c.precision != BFSFT_FP64;
-    dispatch_p2(c.p, [&](auto tag) {
+    dispatch_p(c.p, [&](auto tag) {
         constexpr int P = decltype(tag)::value;
         if (c.d == 2) {
             if (f32)
