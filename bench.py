@@ -31,6 +31,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+WORKLOADS = {
+    "c0": "c0: 2D sparse FT, N=256, p=5, X = K = circle r=0.4, 1 sample per unit length",
+    "c1": "c1: 2D sparse FT, N=4096, p=7, circle r=0.4 targets / r=0.3+0.08cos3t sources",
+    "c2": "c2: 2D sparse FT, N=65536, p=9, circle r=0.4 targets / r=0.3+0.08cos3t sources, "
+          "1 sample per unit length",
+    "c3": "c3: 3D sparse FT, N=256, p=5, X = K = sphere r=0.4, Fibonacci lattice, 1 sample "
+          "per unit area",
+}
 GATE = 1e-6
 COUNTERS = os.path.join(ROOT, "profiles", "translate_c2_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_0801_1524_amd", "csrc", "translate.hip")
@@ -97,7 +105,7 @@ def roofline(res, precision):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_translate2d", "avg_launch_ms": round(t_avg * 1e3, 4),
+            "kernel": "k_translate2d" if info["d"] == 2 else "k_translate3d", "avg_launch_ms": round(t_avg * 1e3, 4),
             "alg_bytes_per_launch": bytes_avg,
             "alg_flops_per_launch": info["sweep_flops"] / L,
             "alg_tflops": round(info["sweep_flops"] / L / t_avg / 1e12, 2)}
@@ -135,6 +143,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precisions", default="mixed,fp64,fp32")
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3"],
+                    help="c2 (default) is the configuration the metric is quoted on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -156,9 +166,9 @@ def main():
         del src, dst
         log("[bench] calibration copy: 1073741824 bytes read, 1073741824 bytes written")
 
-    P = synth.config("c2")
-    S = synth.error_subset(P.nx, 2)
-    log(f"[bench] workload c2: nx={P.nx} nk={P.nk} N={P.N} p={P.p}")
+    P = synth.config(args.workload)
+    S = synth.error_subset(P.nx, synth.CONFIG_NAMES.index(args.workload))
+    log(f"[bench] workload {args.workload}: d={P.d} nx={P.nx} nk={P.nk} N={P.N} p={P.p}")
     results = {}
     for prec in args.precisions.split(","):
         results[prec] = time_precision(bf, torch, P, prec, args.steps, args.warmup)
@@ -187,8 +197,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head in ("fp64", "mixed") else "f32",
         "data": "synthetic",
-        "config": {"workload": "c2: 2D sparse FT, N=65536, p=9, circle r=0.4 targets / "
-                               "r=0.3+0.08cos3t sources, 1 sample per unit length",
+        "config": {"workload": WORKLOADS[args.workload],
                    "nx": P.nx, "nk": P.nk, "levels": r["info"]["levels"], "precision": head,
                    "state_dtype": "f64" if head == "fp64" else "f32"},
         "err_rel_l2": errs[head],

@@ -59,7 +59,7 @@ struct bfsft_plan {
     Tables tb;
     std::vector<int2 *> tiles;    // per T_K level l = 0..L-1 (output level of the step)
     std::vector<int> ntile;
-    std::vector<int> nin_max;     // most children in a tile of level l
+    std::vector<int> cost_max;    // most LDS blocks a tile of level l needs
     std::vector<double *> sig;    // per T_X level m = 0..L-1 (rows a'), null when rho == 1
     void *buf[2] = {nullptr, nullptr};
     size_t state_size = 16;
@@ -114,16 +114,19 @@ Launch launch_of(const bfsft_plan *P)
     return c;
 }
 
-// Tiles of T_K level l: ranges [b0, b1) whose children in level l+1 number at
-// most `maxin` (each box has at most 2^d children, so every tile is non-empty).
-std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int maxin)
+// Tiles of T_K level l: ranges [b0, b1) whose LDS cost (translate_tile_cost
+// of their children count and size) is at most `cap`; a single box always
+// fits, so every tile is non-empty.
+std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap)
 {
     std::vector<int2> t;
     const int n = (int)cb.size() - 1;
     int b0 = 0;
     while (b0 < n) {
         int b1 = b0 + 1;
-        while (b1 < n && cb[b1 + 1] - cb[b0] <= maxin) ++b1;
+        while (b1 < n && cb[b1 + 1] - cb[b0] <= 120 &&
+               translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0) <= cap)
+            ++b1;
         t.push_back(make_int2(b0, b1));
         b0 = b1;
     }
@@ -144,6 +147,8 @@ void check_scalars(int d, int64_t N, int p, int precision, int64_t nx, int64_t n
     if (nx < 0 || nk < 0) throw Error{BFSFT_EINVAL, "negative point count"};
     if (nx > INT32_MAX / 4 || nk > INT32_MAX / 4) throw Error{BFSFT_EINVAL, "too many points"};
     if ((nx > 0 && !x) || (nk > 0 && !k)) throw Error{BFSFT_EINVAL, "NULL point array"};
+    if (!translate_fits(d, p, precision))
+        throw Error{BFSFT_EINVAL, "p too large for d = 3 at this precision (LDS)"};
 }
 
 void build_plan(bfsft_plan *P, const double *x, const double *k)
@@ -156,21 +161,22 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     build_tables(P->tb, P->p, P->N, P->L, P->arena, s);
     P->tiles.assign(P->L, nullptr);
     P->ntile.assign(P->L, 0);
-    P->nin_max.assign(P->L, 0);
+    P->cost_max.assign(P->L, 0);
     P->sig.assign(P->L, nullptr);
     if (P->nx == 0 || P->nk == 0) {
         BF_HIP(hipStreamSynchronize(s));
         return;
     }
-    const int maxin = translate_max_inputs(P->d, P->p, P->precision);
+    const int cap = translate_cap_blocks(P->d, P->p, P->precision);
     size_t maxpairs = 0;
     for (int l = 0; l <= P->L; ++l)
         maxpairs = std::max(maxpairs, (size_t)P->tx.count[P->L - l] * (size_t)P->tk.count[l]);
     for (int l = 0; l < P->L; ++l) {
         const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
-        std::vector<int2> t = make_tiles(cb, maxin);
+        std::vector<int2> t = make_tiles(cb, P->d, cap);
         P->ntile[l] = (int)t.size();
-        for (const int2 &b : t) P->nin_max[l] = std::max(P->nin_max[l], cb[b.y] - cb[b.x]);
+        for (const int2 &b : t)
+            P->cost_max[l] = std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x));
         P->tiles[l] = (int2 *)P->arena.alloc(sizeof(int2) * t.size());
         BF_HIP(hipMemcpyAsync(P->tiles[l], t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice, s));
         BF_HIP(hipStreamSynchronize(s));  // t is a host temporary
@@ -216,7 +222,7 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
         a.k_keys = P->tk.keys[l + 1];
         a.tiles = P->tiles[l];
         a.ntile = P->ntile[l];
-        a.nin_max = P->nin_max[l];
+        a.cost_max = P->cost_max[l];
         a.nap = P->tx.count[L - l - 1];
         a.sig = P->sig[L - l - 1];
         launch_translate(c, a);

@@ -89,7 +89,7 @@ struct LevelArgs {
     const uint64_t *k_keys;  // T_K level l+1 keys (child position s)
     const int2 *tiles;       // [ntile] b ranges
     int ntile;
-    int nin_max;             // most children of any tile
+    int cost_max;            // most LDS blocks any tile needs (translate_tile_cost)
     int64_t nap;             // rows a'
     const double *sig;       // [nap][d] complex exp(2 pi i rho i_{A'}) or null (rho == 1)
 };
@@ -100,7 +100,9 @@ struct Launch {
     hipStream_t stream;
 };
 
-int translate_max_inputs(int d, int p, int precision);
+int translate_cap_blocks(int d, int p, int precision);
+int translate_tile_cost(int d, int nin, int nb);
+bool translate_fits(int d, int p, int precision);
 void launch_translate(const Launch &c, const LevelArgs &a);
 void launch_leaf(const Launch &c, const double *f, const Tree &tk, double rho, void *state);
 void launch_final(const Launch &c, const void *state, const Tree &tx, double rho, int64_t nx,

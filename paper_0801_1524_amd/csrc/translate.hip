@@ -38,7 +38,8 @@ namespace {
 
 constexpr int kTT = 256;       // threads of a translation work-group
 constexpr int kRowsMax = 32;   // rows a' per work-group
-constexpr int kInMax = 160;    // inputs of a tile
+constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
+constexpr size_t kLdsMax = 64 * 1024;  // dynamic LDS of one work-group
 
 struct TArgs {
     const void *in;
@@ -66,128 +67,303 @@ template <int P, int T> struct Rows {
     static constexpr int ndot = (P - first_dot + 1) / 2;
 };
 
-template <int P, int T2, typename S, typename C>
-__device__ __forceinline__ void stage1(const TArgs &a, int R, int64_t ap0, int J0, int nin,
-                                       const int *s_bits, const typename CV<C>::t *s_sig,
-                                       const unsigned char *s_pos, typename CV<C>::t *Y)
+// complex value of type Cv from an LDS/state element of another precision
+template <typename Cv, typename V> __device__ __forceinline__ Cv ld(const V *p)
 {
-    using Sv = typename CV<S>::t;
+    return cvt<Cv>(*p);
+}
+
+template <typename V, typename Cv> __device__ __forceinline__ void st(V *p, const Cv v)
+{
+    V o;
+    o.x = (decltype(o.x))v.x;
+    o.y = (decltype(o.y))v.y;
+    *p = o;
+}
+
+// phase of a child at offset 1 along an axis, output index l, position t:
+// sigma_{A'} * PH_t[l]; sigma = 1 when rho = 1 (RHO1)
+template <bool RHO1, typename Cv, typename C>
+__device__ __forceinline__ Cv child_phase(cptr<C> PH, int t, int l, int P, const Cv sg)
+{
+    const Cv ph = ldc<Cv>(PH, t * P + l);
+    return RHO1 ? ph : cmul(sg, ph);
+}
+
+// stage 1 for one input row x and one output position T2 along axis 2
+template <int P, int T2, bool RHO1, typename C, typename Yv>
+__device__ __forceinline__ void row_interp(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *x,
+                                           bool s2, const typename CV<C>::t sg, Yv *dst)
+{
     using Cv = typename CV<C>::t;
     using RW = Rows<P, T2>;
     constexpr int PP = P * P, Q = P - 1;
-    const cptr<C> Lt = (cptr<C>)(a.Lt);
-    const cptr<C> PH = (cptr<C>)(a.PH);
-    const Sv *in = reinterpret_cast<const Sv *>(a.in);
-    const int per_row = nin * P;
-    for (int v = threadIdx.x; v < R * per_row; v += kTT) {
-        const int r = v / per_row;
-        const int rem = v - r * per_row;
-        const int j = rem / P, l = rem - j * P;
-        if (!(s_bits[r] & (1 << (4 + T2)))) continue;
-        const Sv *src = in + ((ap0 + r) * a.in_row + J0 + j) * PP + l * P;
-        Cv x[P];
-#pragma unroll
-        for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
-        const bool s2 = (s_pos[j] >> 1) & 1;
-        const Cv sg = s_sig[r * 2 + 1];
-        Cv *dst = Y + (r * nin + j) * PP + l * P;
 #pragma unroll 1
-        for (int k = 0; k < RW::ndot; ++k) {
-            const int m = RW::first_dot + 2 * k;
-            Cv y = czero<Cv>();
+    for (int k = 0; k < RW::ndot; ++k) {
+        const int m = RW::first_dot + 2 * k;
+        Cv y = czero<Cv>();
 #pragma unroll
-            for (int mp = 0; mp < P; ++mp) cfma(y, ldc<Cv>(Lt, T2 * PP + m * P + mp), x[mp]);
-            if (s2) y = cmul(y, cmul(sg, ldc<Cv>(PH, T2 * P + m)));
-            dst[m] = y;
-        }
+        for (int mp = 0; mp < P; ++mp) cfma(y, ldc<Cv>(Lt, T2 * PP + m * P + mp), x[mp]);
+        if (s2) y = cmul(y, child_phase<RHO1, Cv>(PH, T2, m, P, sg));
+        st(dst + m, y);
+    }
 #pragma unroll
-        for (int m = 0; m < P; ++m) {
-            if (!RW::copy(m)) continue;
-            Cv y = x[(T2 * Q + m) / 2];
-            if (s2) y = cmul(y, cmul(sg, ldc<Cv>(PH, T2 * P + m)));
-            dst[m] = y;
-        }
+    for (int m = 0; m < P; ++m) {
+        if (!RW::copy(m)) continue;
+        Cv y = x[(T2 * Q + m) / 2];
+        if (s2) y = cmul(y, child_phase<RHO1, Cv>(PH, T2, m, P, sg));
+        st(dst + m, y);
     }
 }
 
-template <int P, int T1, typename S, typename C>
-__device__ __forceinline__ void stage2(const TArgs &a, int R, int t2, int nin, int b0, int nb,
-                                       const int *s_out, const typename CV<C>::t *s_sig,
-                                       const unsigned char *s_pos, const int *s_cb,
-                                       const typename CV<C>::t *Y)
+// stage 2 for one output column (z0: children with s1 = 0, z1: s1 = 1) and
+// output position T1 along axis 1
+template <int P, int T1, bool RHO1, typename S, typename C>
+__device__ __forceinline__ void col_interp(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *z0,
+                                           const typename CV<C>::t *z1, bool h1,
+                                           const typename CV<C>::t sg, typename CV<S>::t *dst)
 {
-    using Sv = typename CV<S>::t;
     using Cv = typename CV<C>::t;
     using RW = Rows<P, T1>;
     constexpr int PP = P * P, Q = P - 1;
+#pragma unroll 1
+    for (int k = 0; k < RW::ndot; ++k) {
+        const int l = RW::first_dot + 2 * k;
+        Cv o0 = czero<Cv>(), o1 = czero<Cv>();
+#pragma unroll
+        for (int lp = 0; lp < P; ++lp) {
+            const Cv lv = ldc<Cv>(Lt, T1 * PP + l * P + lp);
+            cfma(o0, lv, z0[lp]);
+            cfma(o1, lv, z1[lp]);
+        }
+        if (h1) o0 = cadd(o0, cmul(o1, child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
+        st(dst + l * P, o0);
+    }
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        if (!RW::copy(l)) continue;
+        Cv o = z0[(T1 * Q + l) / 2];
+        if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
+        st(dst + l * P, o);
+    }
+}
+
+// (3D kernel below)
+// Y element type: the state precision for the FP32-state paths, FP64 otherwise
+template <typename S, typename C> struct YT { using t = typename CV<S>::t; };
+
+// Strided variant of col_interp: the output column has stride `stride`
+// elements and goes to a destination of element type Dv (LDS or HBM).
+template <int P, int T, bool RHO1, typename C, typename Dv>
+__device__ __forceinline__ void col_interp_s(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *z0,
+                                             const typename CV<C>::t *z1, bool h1,
+                                             const typename CV<C>::t sg, Dv *dst, int stride)
+{
+    using Cv = typename CV<C>::t;
+    using RW = Rows<P, T>;
+    constexpr int PP = P * P, Q = P - 1;
+#pragma unroll 1
+    for (int k = 0; k < RW::ndot; ++k) {
+        const int l = RW::first_dot + 2 * k;
+        Cv o0 = czero<Cv>(), o1 = czero<Cv>();
+#pragma unroll
+        for (int lp = 0; lp < P; ++lp) {
+            const Cv lv = ldc<Cv>(Lt, T * PP + l * P + lp);
+            cfma(o0, lv, z0[lp]);
+            cfma(o1, lv, z1[lp]);
+        }
+        if (h1) o0 = cadd(o0, cmul(o1, child_phase<RHO1, Cv>(PH, T, l, P, sg)));
+        st(dst + l * stride, o0);
+    }
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        if (!RW::copy(l)) continue;
+        Cv o = z0[(T * Q + l) / 2];
+        if (h1) o = cadd(o, cmul(z1[(T * Q + l) / 2], child_phase<RHO1, Cv>(PH, T, l, P, sg)));
+        st(dst + l * stride, o);
+    }
+}
+
+// Step 3, 3D (octrees, p^3 grids, axis 0 = l slowest, axis 2 = n fastest).
+// Child positions s and output positions t carry the parity of axis a in bit
+// a.  Per output position (t2 along axis 2, then t1 along axis 1):
+//   stage 1 (axis 2): rows (j, l, m):  Y1 = L_t2 along n, phase of bit 2,
+//   stage 2 (axis 1): lines (b, e0, l, n): sum the children over bit 2,
+//                     Y2[b][e0] = sum over bit 1 of phase * L_t1 along m,
+//   stage 3 (axis 0): lines (b, m, n): out_t = sum over bit 0 of phase *
+//                     L_t0 along l, written to HBM.
+template <int P, bool RHO1, typename S, typename C>
+__global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
+{
+    using Sv = typename CV<S>::t;
+    using Cv = typename CV<C>::t;
+    using Yv = typename YT<S, C>::t;
+    constexpr int P2 = P * P, P3 = P * P * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_out[kRowsMax * 8];
+    __shared__ int s_bits[kRowsMax];  // bit t: output t; bit 8+t2: some output with t2;
+                                      // bit 16 + 2*t2 + t1: some output with (t1, t2)
+    __shared__ Cv s_sig[kRowsMax * 3];
+    __shared__ unsigned char s_pos[kInMax];
+    __shared__ signed char s_cj[kInMax * 8];
+
+    const int64_t gid = blockIdx.x;
+    const int64_t g = gid / a.ntile;
+    const int tile = (int)(gid - g * a.ntile);
+    const int64_t ap0 = g * a.rows;
+    const int R = (int)min((int64_t)a.rows, a.nap - ap0);
+    const int2 bt = a.tiles[tile];
+    const int b0 = bt.x, nb = bt.y - bt.x;
+    const int J0 = a.k_cb[b0];
+    const int nin = a.k_cb[bt.y] - J0;
+    Yv *Y1 = reinterpret_cast<Yv *>(smem);  // [R][nin][P3]
+    Yv *Y2 = Y1 + R * nin * P3;             // [R][nb][2][P3]
+
+    for (int i = threadIdx.x; i < nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[J0 + i] & 7);
+    for (int bl = threadIdx.x; bl < nb; bl += kTT) {
+        signed char cj[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        for (int j = a.k_cb[b0 + bl]; j < a.k_cb[b0 + bl + 1]; ++j)
+            cj[a.k_keys[j] & 7] = (signed char)(j - J0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_cj[bl * 8 + s] = cj[s];
+    }
+    if (threadIdx.x < R) {
+        const int r = threadIdx.x;
+        const int64_t ap = ap0 + r;
+        int bits = 0;
+        int o[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        for (int i = a.x_cb[ap]; i < a.x_cb[ap + 1]; ++i) {
+            const int t = (int)(a.x_keys[i] & 7);
+            o[t] = i;
+            bits |= (1 << t) | (1 << (8 + (t >> 2))) | (1 << (16 + 2 * (t >> 2) + ((t >> 1) & 1)));
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s_out[r * 8 + t] = o[t];
+        s_bits[r] = bits;
+        Cv one;
+        one.x = 1;
+        one.y = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) s_sig[r * 3 + ax] = a.sig ? cvt<Cv>(a.sig[ap * 3 + ax]) : one;
+    }
+    __syncthreads();
+    int all = 0;
+    for (int r = 0; r < R; ++r) all |= s_bits[r];
+
     const cptr<C> Lt = (cptr<C>)(a.Lt);
     const cptr<C> PH = (cptr<C>)(a.PH);
-    Sv *out = reinterpret_cast<Sv *>(a.out);
-    const int t = T1 | (t2 << 1);
-    const int per_row = nb * P;
-    for (int v = threadIdx.x; v < R * per_row; v += kTT) {
-        const int r = v / per_row;
-        const int rem = v - r * per_row;
-        const int bl = rem / P, m = rem - bl * P;
-        const int ao = s_out[r * 4 + t];
-        if (ao < 0) continue;
-        Cv z0[P], z1[P];
+    for (int t2 = 0; t2 < 2; ++t2) {
+        if (!(all & (1 << (8 + t2)))) continue;
+        // stage 1
+        for (int r = 0; r < R; ++r) {
+            if (!(s_bits[r] & (1 << (8 + t2)))) continue;
+            const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * P3;
+            Yv *Yr = Y1 + r * nin * P3;
+            const Cv sg = s_sig[r * 3 + 2];
+            for (int v = threadIdx.x; v < nin * P2; v += kTT) {
+                const int j = v / P2;
+                const Sv *src = in + v * P;
+                Cv x[P];
 #pragma unroll
-        for (int l = 0; l < P; ++l) z0[l] = z1[l] = czero<Cv>();
-        bool h1 = false;
-        for (int j = s_cb[bl]; j < s_cb[bl + 1]; ++j) {
-            const Cv *yp = Y + (r * nin + j) * PP + m;
-            if (s_pos[j] & 1) {
-                h1 = true;
-#pragma unroll
-                for (int l = 0; l < P; ++l) z1[l] = cadd(z1[l], yp[l * P]);
-            } else {
-#pragma unroll
-                for (int l = 0; l < P; ++l) z0[l] = cadd(z0[l], yp[l * P]);
+                for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
+                const bool e2 = (s_pos[j] >> 2) & 1;
+                if (t2 == 0)
+                    row_interp<P, 0, RHO1, C>(Lt, PH, x, e2, sg, Yr + v * P);
+                else
+                    row_interp<P, 1, RHO1, C>(Lt, PH, x, e2, sg, Yr + v * P);
             }
         }
-        const Cv sg = s_sig[r * 2];
-        Sv *dst = out + ((int64_t)ao * a.out_row + b0 + bl) * PP + m;
-#pragma unroll 1
-        for (int k = 0; k < RW::ndot; ++k) {
-            const int l = RW::first_dot + 2 * k;
-            Cv o0 = czero<Cv>(), o1 = czero<Cv>();
+        __syncthreads();
+        for (int t1 = 0; t1 < 2; ++t1) {
+            if (!(all & (1 << (16 + 2 * t2 + t1)))) continue;
+            // stage 2: lines along m, for (b, e0, l, n)
+            for (int r = 0; r < R; ++r) {
+                if (!(s_bits[r] & (1 << (16 + 2 * t2 + t1)))) continue;
+                const Yv *Yr = Y1 + r * nin * P3;
+                Yv *Y2r = Y2 + r * nb * 2 * P3;
+                const Cv sg = s_sig[r * 3 + 1];
+                for (int v = threadIdx.x; v < nb * 2 * P2; v += kTT) {
+                    const int bl = v / (2 * P2);
+                    const int rem = v - bl * 2 * P2;
+                    const int e0 = rem / P2;
+                    const int ln = rem - e0 * P2;
+                    const int l = ln / P, n = ln - l * P;
+                    Cv z0[P], z1[P];
 #pragma unroll
-            for (int lp = 0; lp < P; ++lp) {
-                const Cv lv = ldc<Cv>(Lt, T1 * PP + l * P + lp);
-                cfma(o0, lv, z0[lp]);
-                cfma(o1, lv, z1[lp]);
+                    for (int m = 0; m < P; ++m) z0[m] = z1[m] = czero<Cv>();
+                    bool h1 = false;
+#pragma unroll
+                    for (int e12 = 0; e12 < 4; ++e12) {  // e1 = bit 0 of e12, e2 = bit 1
+                        const int c = s_cj[bl * 8 + e0 + 2 * e12];
+                        if (c < 0) continue;
+                        const Yv *yp = Yr + c * P3 + l * P2 + n;
+                        if (e12 & 1) {
+                            h1 = true;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) z1[m] = cadd(z1[m], ld<Cv>(yp + m * P));
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) z0[m] = cadd(z0[m], ld<Cv>(yp + m * P));
+                        }
+                    }
+                    Yv *dst = Y2r + (bl * 2 + e0) * P3 + l * P2 + n;
+                    if (t1 == 0)
+                        col_interp_s<P, 0, RHO1, C>(Lt, PH, z0, z1, h1, sg, dst, P);
+                    else
+                        col_interp_s<P, 1, RHO1, C>(Lt, PH, z0, z1, h1, sg, dst, P);
+                }
             }
-            if (h1) o0 = cadd(o0, cmul(o1, cmul(sg, ldc<Cv>(PH, T1 * P + l))));
-            Sv so;
-            so.x = (S)o0.x;
-            so.y = (S)o0.y;
-            dst[l * P] = so;
-        }
+            __syncthreads();
+            // stage 3: lines along l, for (b, m, n); both output positions t0
+            for (int r = 0; r < R; ++r) {
+                const int bits = s_bits[r];
+                if (!(bits & (1 << (16 + 2 * t2 + t1)))) continue;
+                const Yv *Y2r = Y2 + r * nb * 2 * P3;
+                const Cv sg = s_sig[r * 3 + 0];
+                const int ta = 4 * t2 + 2 * t1;
+                const int a0 = s_out[r * 8 + ta], a1 = s_out[r * 8 + ta + 1];
+                for (int v = threadIdx.x; v < nb * P2; v += kTT) {
+                    const int bl = v / P2, mn = v - bl * P2;
+                    Cv z0[P], z1[P];
+                    const Yv *y0 = Y2r + (bl * 2 + 0) * P3 + mn;
+                    const Yv *y1 = Y2r + (bl * 2 + 1) * P3 + mn;
+                    const bool h1 = (s_cj[bl * 8 + 1] >= 0) | (s_cj[bl * 8 + 3] >= 0) |
+                                    (s_cj[bl * 8 + 5] >= 0) | (s_cj[bl * 8 + 7] >= 0);
+                    const bool h0 = (s_cj[bl * 8 + 0] >= 0) | (s_cj[bl * 8 + 2] >= 0) |
+                                    (s_cj[bl * 8 + 4] >= 0) | (s_cj[bl * 8 + 6] >= 0);
 #pragma unroll
-        for (int l = 0; l < P; ++l) {
-            if (!RW::copy(l)) continue;
-            Cv o = z0[(T1 * Q + l) / 2];
-            if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], cmul(sg, ldc<Cv>(PH, T1 * P + l))));
-            Sv so;
-            so.x = (S)o.x;
-            so.y = (S)o.y;
-            dst[l * P] = so;
+                    for (int l = 0; l < P; ++l) {
+                        z0[l] = h0 ? ld<Cv>(y0 + l * P2) : czero<Cv>();
+                        z1[l] = h1 ? ld<Cv>(y1 + l * P2) : czero<Cv>();
+                    }
+                    if (a0 >= 0)
+                        col_interp_s<P, 0, RHO1, C>(Lt, PH, z0, z1, h1, sg,
+                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2);
+                    if (a1 >= 0)
+                        col_interp_s<P, 1, RHO1, C>(Lt, PH, z0, z1, h1, sg,
+                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2);
+                }
+            }
+            __syncthreads();
         }
     }
 }
 
-template <int P, typename S, typename C>
+
+template <int P, bool RHO1, typename S, typename C>
 __global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
 {
+    using Sv = typename CV<S>::t;
     using Cv = typename CV<C>::t;
+    using Yv = typename YT<S, C>::t;
+    constexpr int PP = P * P;
     extern __shared__ __align__(16) unsigned char smem[];
-    Cv *Y = reinterpret_cast<Cv *>(smem);
+    Yv *Y = reinterpret_cast<Yv *>(smem);  // [2 t2][R][nin][P][P]
     __shared__ int s_out[kRowsMax * 4];
     __shared__ int s_bits[kRowsMax];
     __shared__ Cv s_sig[kRowsMax * 2];
     __shared__ unsigned char s_pos[kInMax];
-    __shared__ int s_cb[kInMax + 1];
+    __shared__ signed char s_cj[kInMax * 4];  // [b][s]: local child index or -1
 
     const int64_t gid = blockIdx.x;
     const int64_t g = gid / a.ntile;
@@ -200,7 +376,13 @@ __global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
     const int nin = a.k_cb[bt.y] - J0;
 
     for (int i = threadIdx.x; i < nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[J0 + i] & 3);
-    for (int i = threadIdx.x; i <= nb; i += kTT) s_cb[i] = a.k_cb[b0 + i] - J0;
+    for (int bl = threadIdx.x; bl < nb; bl += kTT) {
+        signed char cj[4] = {-1, -1, -1, -1};
+        for (int j = a.k_cb[b0 + bl]; j < a.k_cb[b0 + bl + 1]; ++j)
+            cj[a.k_keys[j] & 3] = (signed char)(j - J0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) s_cj[bl * 4 + s] = cj[s];
+    }
     if (threadIdx.x < R) {
         const int r = threadIdx.x;
         const int64_t ap = ap0 + r;
@@ -221,21 +403,74 @@ __global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
         s_sig[r * 2 + 1] = a.sig ? cvt<Cv>(a.sig[ap * 2 + 1]) : one;
     }
     __syncthreads();
-    int all = 0;
-    for (int r = 0; r < R; ++r) all |= s_bits[r];
 
-    for (int t2 = 0; t2 < 2; ++t2) {
-        if (!(all & (1 << (4 + t2)))) continue;
-        if (t2 == 0)
-            stage1<P, 0, S, C>(a, R, ap0, J0, nin, s_bits, s_sig, s_pos, Y);
-        else
-            stage1<P, 1, S, C>(a, R, ap0, J0, nin, s_bits, s_sig, s_pos, Y);
-        __syncthreads();
-        if (all & (1 << (t2 << 1)))
-            stage2<P, 0, S, C>(a, R, t2, nin, b0, nb, s_out, s_sig, s_pos, s_cb, Y);
-        if (all & (1 << (1 | (t2 << 1))))
-            stage2<P, 1, S, C>(a, R, t2, nin, b0, nb, s_out, s_sig, s_pos, s_cb, Y);
-        __syncthreads();
+    const cptr<C> Lt = (cptr<C>)(a.Lt);
+    const cptr<C> PH = (cptr<C>)(a.PH);
+    const int ysz = R * nin * PP;  // one t2 half of Y
+
+    // stage 1: every input row once, both output positions t2 it is needed for
+    for (int r = 0; r < R; ++r) {
+        const int bits = s_bits[r];  // uniform
+        const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * PP;
+        Yv *Yr = Y + r * nin * PP;
+        const Cv sg = s_sig[r * 2 + 1];
+        for (int v = threadIdx.x; v < nin * P; v += kTT) {
+            const int j = v / P;
+            const Sv *src = in + v * P;
+            Cv x[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
+            const bool s2 = (s_pos[j] >> 1) & 1;
+            if (bits & (1 << 4)) row_interp<P, 0, RHO1, C>(Lt, PH, x, s2, sg, Yr + v * P);
+            if (bits & (1 << 5)) row_interp<P, 1, RHO1, C>(Lt, PH, x, s2, sg, Yr + ysz + v * P);
+        }
+    }
+    __syncthreads();
+
+    // stage 2: every output column once per t2, both output positions t1
+    for (int r = 0; r < R; ++r) {
+        const int bits = s_bits[r];
+        const Cv sg = s_sig[r * 2];
+        for (int t2 = 0; t2 < 2; ++t2) {
+            if (!(bits & (1 << (4 + t2)))) continue;  // uniform
+            const Yv *Yr = Y + t2 * ysz + r * nin * PP;
+            const int a0 = s_out[r * 4 + (t2 << 1)], a1 = s_out[r * 4 + 1 + (t2 << 1)];
+            for (int v = threadIdx.x; v < nb * P; v += kTT) {
+                const int bl = v / P, m = v - bl * P;
+                const int c0 = s_cj[bl * 4 + 0], c2 = s_cj[bl * 4 + 2];
+                const int c1 = s_cj[bl * 4 + 1], c3 = s_cj[bl * 4 + 3];
+                Cv z0[P], z1[P];
+#pragma unroll
+                for (int l = 0; l < P; ++l) z0[l] = z1[l] = czero<Cv>();
+                if (c0 >= 0) {
+                    const Yv *yp = Yr + c0 * PP + m;
+#pragma unroll
+                    for (int l = 0; l < P; ++l) z0[l] = ld<Cv>(yp + l * P);
+                }
+                if (c2 >= 0) {
+                    const Yv *yp = Yr + c2 * PP + m;
+#pragma unroll
+                    for (int l = 0; l < P; ++l) z0[l] = cadd(z0[l], ld<Cv>(yp + l * P));
+                }
+                if (c1 >= 0) {
+                    const Yv *yp = Yr + c1 * PP + m;
+#pragma unroll
+                    for (int l = 0; l < P; ++l) z1[l] = ld<Cv>(yp + l * P);
+                }
+                if (c3 >= 0) {
+                    const Yv *yp = Yr + c3 * PP + m;
+#pragma unroll
+                    for (int l = 0; l < P; ++l) z1[l] = cadd(z1[l], ld<Cv>(yp + l * P));
+                }
+                const bool h1 = (c1 >= 0) | (c3 >= 0);
+                if (a0 >= 0)
+                    col_interp<P, 0, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
+                        reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m);
+                if (a1 >= 0)
+                    col_interp<P, 1, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
+                        reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m);
+            }
+        }
     }
 }
 
@@ -251,20 +486,33 @@ int lds_budget()
 
 }  // namespace
 
-int translate_max_inputs(int d, int p, int precision)
+// LDS blocks (p^d elements of the intermediate type) a work-group may hold
+int translate_cap_blocks(int d, int p, int precision)
 {
-    const int csize = precision == BFSFT_FP32 ? 8 : 16;
     int PD = p;
     for (int a = 1; a < d; ++a) PD *= p;
-    int m = lds_budget() / (PD * csize);
-    if (m > kInMax) m = kInMax;
-    if (m < (1 << d)) m = 1 << d;
-    return m;
+    const int elem = precision == BFSFT_FP64 ? 16 : 8;
+    int cap = lds_budget() / (PD * elem);
+    const int one_box = d == 2 ? 2 * 4 : 8 + 2;  // a single box with all children
+    if (cap < one_box) cap = one_box;
+    return cap;
 }
 
-int translate_rows(int d, int p, int precision, int nin_max, int64_t nap)
+// LDS blocks a tile of nb boxes with nin children needs
+int translate_tile_cost(int d, int nin, int nb) { return d == 2 ? 2 * nin : nin + 2 * nb; }
+
+bool translate_fits(int d, int p, int precision)
 {
-    int R = translate_max_inputs(d, p, precision) / std::max(1, nin_max);
+    int PD = p;
+    for (int a = 1; a < d; ++a) PD *= p;
+    const int elem = precision == BFSFT_FP64 ? 16 : 8;
+    const int one_box = d == 2 ? 2 * 4 : 8 + 2;
+    return (size_t)one_box * PD * elem <= kLdsMax;
+}
+
+int translate_rows(int d, int p, int precision, int cost_max, int64_t nap)
+{
+    int R = translate_cap_blocks(d, p, precision) / std::max(1, cost_max);
     R = std::max(1, std::min(R, kRowsMax));
     return (int)std::min<int64_t>(R, std::max<int64_t>(1, nap));
 }
@@ -272,7 +520,6 @@ int translate_rows(int d, int p, int precision, int nin_max, int64_t nap)
 void launch_translate(const Launch &c, const LevelArgs &la)
 {
     if (la.nap == 0 || la.ntile == 0) return;
-    if (c.d != 2) throw Error{BFSFT_EINVAL, "3D translation not built"};
     TArgs a;
     a.in = la.in;
     a.out = la.out;
@@ -285,22 +532,42 @@ void launch_translate(const Launch &c, const LevelArgs &la)
     a.tiles = la.tiles;
     a.ntile = la.ntile;
     a.nap = la.nap;
-    a.rows = translate_rows(c.d, c.p, c.precision, la.nin_max, la.nap);
+    a.rows = translate_rows(c.d, c.p, c.precision, la.cost_max, la.nap);
     a.sig = reinterpret_cast<const double2 *>(la.sig);
     const bool f32 = c.precision == BFSFT_FP32;
     a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
     a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
     const int64_t groups = (la.nap + a.rows - 1) / a.rows;
     const int64_t grid = groups * la.ntile;
-    dispatch_p(c.p, [&](auto tag) {
+    auto body = [&](auto tag, auto *sp, auto *cp, auto d3) {
         constexpr int P = decltype(tag)::value;
-        dispatch_prec(c.precision, [&](auto *sp, auto *cp) {
-            using S = std::remove_pointer_t<decltype(sp)>;
-            using C = std::remove_pointer_t<decltype(cp)>;
-            const size_t lds = (size_t)a.rows * la.nin_max * P * P * sizeof(typename CV<C>::t);
-            k_translate2d<P, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using C = std::remove_pointer_t<decltype(cp)>;
+        constexpr bool D3 = decltype(d3)::value;
+        const size_t PD = D3 ? (size_t)P * P * P : (size_t)P * P;
+        const size_t lds = (size_t)a.rows * la.cost_max * PD * sizeof(typename YT<S, C>::t);
+        if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
+        if constexpr (D3) {
+            if (la.sig)
+                k_translate3d<P, false, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+            else
+                k_translate3d<P, true, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+        } else {
+            if (la.sig)
+                k_translate2d<P, false, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+            else
+                k_translate2d<P, true, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+        }
+    };
+    if (c.d == 2) {
+        dispatch_p(c.p, [&](auto tag) {
+            dispatch_prec(c.precision, [&](auto *sp, auto *cp) { body(tag, sp, cp, std::false_type{}); });
         });
-    });
+    } else {
+        dispatch_p3(c.p, [&](auto tag) {
+            dispatch_prec(c.precision, [&](auto *sp, auto *cp) { body(tag, sp, cp, std::true_type{}); });
+        });
+    }
     BF_HIP(hipGetLastError());
 }
 

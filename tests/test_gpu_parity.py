@@ -204,3 +204,75 @@ def test_c2_full_size_vs_oracle_sampled_targets(bf, oracle_mod, c2):
     u = gpu_u(bf, c2, "fp64")
     ub = oracle_mod.Butterfly(c2.d, c2.N, c2.p, c2.x[S], c2.k).run(c2.f)
     assert rel_l2(u[S], ub) <= 1e-10
+
+
+# ----------------------------------------------------------------------- 3D
+
+@pytest.mark.parametrize("p", [3, 4, 5, 6])
+def test_3d_fp64_vs_oracle(bf, oracle_mod, p):
+    N = 16
+    x = synth.sphere(N)
+    k = synth.sphere(N, radius=0.3)
+    f = synth.gaussian_sources(k.shape[0], p)
+    P = synth.Problem("sph", 3, N, p, x, k, f)
+    assert rel_l2(gpu_u(bf, P), oracle_u(oracle_mod, P)) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
+def test_3d_sphere_vs_oracle_and_direct(bf, oracle_mod, precision):
+    N, p = 32, 5
+    x = synth.sphere(N)
+    k = x.copy()
+    f = synth.gaussian_sources(k.shape[0], 3)
+    P = synth.Problem("sph32", 3, N, p, x, k, f)
+    u = gpu_u(bf, P, precision)
+    assert rel_l2(u, oracle_u(oracle_mod, P)) <= TOL_O2[precision]
+    assert rel_l2(u, oracle_mod.direct(x, k, f, N)) <= EPS[p]
+
+
+def test_3d_non_power_of_two(bf, oracle_mod):
+    N = 24  # L = 5, rho = 0.75
+    x = synth.sphere(N)
+    k = synth.sphere(N, radius=0.35)
+    f = synth.gaussian_sources(k.shape[0], 9)
+    P = synth.Problem("sph24", 3, N, 4, x, k, f)
+    assert rel_l2(gpu_u(bf, P), oracle_u(oracle_mod, P)) <= 1e-10
+
+
+def test_3d_level_potentials(bf, oracle_mod):
+    N, p = 16, 5
+    x = synth.sphere(N)
+    k = synth.sphere(N, radius=0.3)
+    f = synth.gaussian_sources(k.shape[0], 2)
+    ob = oracle_mod.Butterfly(3, N, p, x, k)
+    lvl = 2
+    _, du, _ = ob.run(f, dump_level=lvl)
+    with bf.Plan(3, N, p, x, k, "fp64") as plan:
+        _, pot = plan.execute_probe(f, lvl)
+        pot = pot.cpu().numpy()
+        gx, gk = plan.boxes("x", ob.L - lvl), plan.boxes("k", lvl)
+    ix = {tuple(r): i for i, r in enumerate(ob.boxes("x", ob.L - lvl))}
+    ik = {tuple(r): i for i, r in enumerate(ob.boxes("k", lvl))}
+    ref = du[np.array([ix[tuple(r)] for r in gx])][:, np.array([ik[tuple(r)] for r in gk])]
+    assert rel_l2(pot, ref) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return synth.config("c3")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c3_full_size_vs_direct_subset(bf, oracle_mod, c3, precision):
+    """3D, N = 256, p = 5 at full size (131,768 points each side)."""
+    S = synth.error_subset(c3.nx, 3)
+    u = gpu_u(bf, c3, precision)
+    assert rel_l2(u[S], oracle_mod.direct(c3.x, c3.k, c3.f, c3.N, S)) <= EPS[5]
+
+
+def test_c3_full_size_vs_oracle_sampled_targets(bf, oracle_mod, c3):
+    rng = np.random.default_rng(23)
+    S = np.sort(rng.choice(c3.nx, 6, replace=False))
+    u = gpu_u(bf, c3, "fp64")
+    ub = oracle_mod.Butterfly(c3.d, c3.N, c3.p, c3.x[S], c3.k).run(c3.f)
+    assert rel_l2(u[S], ub) <= 1e-10
