@@ -59,13 +59,17 @@ typedef struct {
     double rho;                           /* leaf width N / 2^L */
     int64_t x_boxes[BFSFT_MAX_LEVELS + 1];/* non-empty T_X boxes at level m = 0..L */
     int64_t k_boxes[BFSFT_MAX_LEVELS + 1];/* non-empty T_K boxes at level m = 0..L */
-    int64_t pairs[BFSFT_MAX_LEVELS + 1];  /* box pairs at T_K level l: x_boxes[L-l] * k_boxes[l] */
+    int64_t pairs[BFSFT_MAX_LEVELS + 1];  /* box pairs at T_K level l: x_boxes[L-l] * k_boxes[l];
+                                             batched: pairs produced at sweep step s, all
+                                             transforms */
     double sweep_bytes;                   /* algorithmic HBM bytes of the sweep (read + write
                                              of every level's state, once) */
     double sweep_flops;                   /* algorithmic flops of the sweep: per output pair,
                                              2^d * d * p^(d+1) complex multiply-adds x 8 */
     int64_t device_bytes;                 /* device memory owned by the plan */
     int64_t transforms;                   /* 1, or the count of a batched plan */
+    int lds_kb;                           /* LDS budget of a translation tile (tuned) */
+    int wg_per_cu;                        /* batched: persistent work-groups per CU (tuned) */
 } bfsft_info;
 
 /*
@@ -85,7 +89,12 @@ typedef struct {
  * The points are copied; the caller may free x and k when this returns (the
  * call synchronises the stream).  Box index of a point along an axis:
  * min(floor(x * 2^L / N), 2^L - 1) in IEEE FP64 (half-open boxes).
- * Environment: BFSFT_MAX_DEVICE_BYTES caps the plan's device memory.
+ * Environment: BFSFT_MAX_DEVICE_BYTES caps the plan's device memory;
+ * BFSFT_AUTOTUNE=0 disables the plan-time tuning of the translation tiles
+ * (otherwise the sweep is timed on the plan's own shapes for a few tile LDS
+ * budgets and the fastest is kept; results do not depend on the choice);
+ * BFSFT_TUNE_CACHE names the text file caching tuned choices (default
+ * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget.
  */
 int bfsft_plan_create(bfsft_plan **out, int d, int64_t N, int p, int precision,
                       const double *x, int64_t nx, const double *k, int64_t nk,

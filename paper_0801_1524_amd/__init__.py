@@ -41,6 +41,7 @@ class Info(ctypes.Structure):
         ("pairs", ctypes.c_int64 * (MAX_LEVELS + 1)),
         ("sweep_bytes", ctypes.c_double), ("sweep_flops", ctypes.c_double),
         ("device_bytes", ctypes.c_int64), ("transforms", ctypes.c_int64),
+        ("lds_kb", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
     ]
 
 
@@ -128,6 +129,7 @@ def _info_dict(info: Info) -> dict:
         "pairs": list(info.pairs[:L + 1]),
         "sweep_bytes": info.sweep_bytes, "sweep_flops": info.sweep_flops,
         "device_bytes": info.device_bytes, "transforms": info.transforms,
+        "lds_kb": info.lds_kb, "wg_per_cu": info.wg_per_cu,
     }
 
 

@@ -1,17 +1,27 @@
 // C ABI of bfsft (include/bfsft.h): validation, plan construction and the
-// stream-ordered execution of steps 2-4 of Section 2.2.
-#include "bfsft_impl.h"
+// stream-ordered execution of steps 2-4 of Section 2.2 for one transform.
+// Batched plans live in batched.hip.
+#include "plan.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 
 namespace bfsft {
 
 int validate_points(const double *pts, int64_t n, int d, int64_t N, hipStream_t s);
+
+// batched.hip
+void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs);
+void execute_batched(bfsft_plan *B, const double *f, double *u, bool serial);
+void release_batched(bfsft_plan *B);
+void info_batched(const bfsft_plan *B, bfsft_info *o);
 
 namespace {
 thread_local std::string g_last_error;
@@ -44,32 +54,6 @@ void Arena::release()
     bytes = 0;
 }
 
-}  // namespace bfsft
-
-using namespace bfsft;
-
-struct bfsft_plan {
-    int d = 0, p = 0, precision = 0, L = 0;
-    int64_t N = 0, nx = 0, nk = 0;
-    double rho = 1.0;
-    int PD = 0;
-    hipStream_t stream = nullptr;
-    Arena arena;
-    Tree tx, tk;
-    Tables tb;
-    std::vector<int2 *> tiles;    // per T_K level l = 0..L-1 (output level of the step)
-    std::vector<int> ntile;
-    std::vector<int> cost_max;    // most LDS blocks a tile of level l needs
-    std::vector<double *> sig;    // per T_X level m = 0..L-1 (rows a'), null when rho == 1
-    void *buf[2] = {nullptr, nullptr};
-    size_t state_size = 16;
-    // timing events: per execute, L + 3 of them (see bfsft_timing_begin)
-    std::vector<hipEvent_t> tev;
-    int tmax = 0, tcount = 0;
-};
-
-namespace {
-
 int ceil_log2(int64_t N)
 {
     int L = 0;
@@ -84,6 +68,61 @@ int64_t env_cap()
     char *end = nullptr;
     long long v = std::strtoll(s, &end, 10);
     return v < 0 ? -1 : (int64_t)v;
+}
+
+Launch launch_of(const bfsft_plan *P)
+{
+    Launch c;
+    c.d = P->d;
+    c.p = P->p;
+    c.precision = P->precision;
+    c.tb = &P->tb;
+    c.stream = P->stream;
+    return c;
+}
+
+// Arguments of the translation producing T_K level l (rows a' at T_X level
+// L-l-1, outputs at T_X level L-l).
+LevelArgs level_args(const bfsft_plan *P, int l, const void *in, void *out)
+{
+    const int L = P->L;
+    LevelArgs a;
+    a.in = in;
+    a.out = out;
+    a.in_row = P->tk.count[l + 1];
+    a.out_row = P->tk.count[l];
+    a.x_cb = P->tx.child_beg[L - l - 1];
+    a.x_keys = P->tx.keys[L - l];
+    a.k_cb = P->tk.child_beg[l];
+    a.k_keys = P->tk.keys[l + 1];
+    a.tiles = P->tiles[l];
+    a.ntile = P->ntile[l];
+    a.cost_max = P->cost_max[l];
+    a.rows = P->rows[l];
+    a.nap = P->tx.count[L - l - 1];
+    a.sig = P->sig[L - l - 1];
+    return a;
+}
+
+namespace {
+
+// Tiles of T_K level l: ranges [b0, b1) whose LDS cost (translate_tile_cost
+// of their children count and size) is at most `cap`, with at most 120
+// children; a single box always fits, so every tile is non-empty.
+std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap)
+{
+    std::vector<int2> t;
+    const int n = (int)cb.size() - 1;
+    int b0 = 0;
+    while (b0 < n) {
+        int b1 = b0 + 1;
+        while (b1 < n && cb[b1 + 1] - cb[b0] <= 120 &&
+               translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0) <= cap)
+            ++b1;
+        t.push_back(make_int2(b0, b1));
+        b0 = b1;
+    }
+    return t;
 }
 
 template <typename F> int guarded(F &&f)
@@ -101,36 +140,6 @@ template <typename F> int guarded(F &&f)
         set_last_error("unexpected exception");
         return BFSFT_EDEVICE;
     }
-}
-
-Launch launch_of(const bfsft_plan *P)
-{
-    Launch c;
-    c.d = P->d;
-    c.p = P->p;
-    c.precision = P->precision;
-    c.tb = &P->tb;
-    c.stream = P->stream;
-    return c;
-}
-
-// Tiles of T_K level l: ranges [b0, b1) whose LDS cost (translate_tile_cost
-// of their children count and size) is at most `cap`; a single box always
-// fits, so every tile is non-empty.
-std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap)
-{
-    std::vector<int2> t;
-    const int n = (int)cb.size() - 1;
-    int b0 = 0;
-    while (b0 < n) {
-        int b1 = b0 + 1;
-        while (b1 < n && cb[b1 + 1] - cb[b0] <= 120 &&
-               translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0) <= cap)
-            ++b1;
-        t.push_back(make_int2(b0, b1));
-        b0 = b1;
-    }
-    return t;
 }
 
 void check_scalars(int d, int64_t N, int p, int precision, int64_t nx, int64_t nk, const void *x,
@@ -151,46 +160,93 @@ void check_scalars(int d, int64_t N, int p, int precision, int64_t nx, int64_t n
         throw Error{BFSFT_EINVAL, "p too large for d = 3 at this precision (LDS)"};
 }
 
-void build_plan(bfsft_plan *P, const double *x, const double *k)
+void init_plan(bfsft_plan *P, int d, int64_t N, int p, int precision, int64_t nx, int64_t nk,
+               hipStream_t stream)
 {
-    hipStream_t s = P->stream;
-    if (validate_points(x, P->nx, P->d, P->N, s) || validate_points(k, P->nk, P->d, P->N, s))
-        throw Error{BFSFT_EDOMAIN, "a coordinate is not finite or lies outside [0, N]"};
-    build_tree(P->tx, x, P->nx, P->d, P->L, P->N, P->arena, s);
-    build_tree(P->tk, k, P->nk, P->d, P->L, P->N, P->arena, s);
-    build_tables(P->tb, P->p, P->N, P->L, P->arena, s);
-    P->tiles.assign(P->L, nullptr);
-    P->ntile.assign(P->L, 0);
-    P->cost_max.assign(P->L, 0);
-    P->sig.assign(P->L, nullptr);
-    if (P->nx == 0 || P->nk == 0) {
-        BF_HIP(hipStreamSynchronize(s));
+    P->d = d;
+    P->p = p;
+    P->precision = precision;
+    P->N = N;
+    P->nx = nx;
+    P->nk = nk;
+    P->L = ceil_log2(N);
+    P->rho = std::ldexp((double)N, -P->L);
+    P->PD = d == 2 ? p * p : p * p * p;
+    P->stream = stream;
+    P->state_size = precision == BFSFT_FP64 ? 16 : 8;
+    P->arena.cap = env_cap();
+}
+
+const char *prec_name(int precision)
+{
+    return precision == BFSFT_FP64 ? "fp64" : precision == BFSFT_MIXED ? "mixed" : "fp32";
+}
+
+size_t state_bytes(const bfsft_plan *P)
+{
+    size_t m = 0;
+    for (int l = 0; l <= P->L; ++l)
+        m = std::max(m, (size_t)P->tx.count[P->L - l] * (size_t)P->tk.count[l]);
+    return m * P->PD * P->state_size;
+}
+
+// Time one sweep (all levels) of a single plan, eagerly; best of `reps`
+// after one warm-up, milliseconds.
+double time_sweep(bfsft_plan *P, int reps)
+{
+    const Launch c = launch_of(P);
+    hipEvent_t e0, e1;
+    BF_HIP(hipEventCreate(&e0));
+    BF_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    for (int r = 0; r < reps + 1; ++r) {
+        BF_HIP(hipEventRecord(e0, P->stream));
+        int cur = 0;
+        for (int l = P->L - 1; l >= 0; --l) {
+            launch_translate(c, level_args(P, l, P->buf[cur], P->buf[cur ^ 1]));
+            cur ^= 1;
+        }
+        BF_HIP(hipEventRecord(e1, P->stream));
+        BF_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        BF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0) best = std::min(best, (double)ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+// Choose the tile LDS budget of a single plan by timing its sweep on its own
+// shapes.  The tiling does not change any result (every output is computed
+// by the same operations in the same order), only the speed.  Cached per
+// (architecture, d, p, precision, L).
+void autotune_single(bfsft_plan *P)
+{
+    const std::string key = "single/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
+                            prec_name(P->precision) + "/L" + std::to_string(P->L);
+    std::vector<int> v;
+    if (tune_lookup(key, v) && v.size() == 1) {
+        build_tiles(P, v[0] * 1024);
         return;
     }
-    const int cap = translate_cap_blocks(P->d, P->p, P->precision);
-    size_t maxpairs = 0;
-    for (int l = 0; l <= P->L; ++l)
-        maxpairs = std::max(maxpairs, (size_t)P->tx.count[P->L - l] * (size_t)P->tk.count[l]);
-    for (int l = 0; l < P->L; ++l) {
-        const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
-        std::vector<int2> t = make_tiles(cb, P->d, cap);
-        P->ntile[l] = (int)t.size();
-        for (const int2 &b : t)
-            P->cost_max[l] = std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x));
-        P->tiles[l] = (int2 *)P->arena.alloc(sizeof(int2) * t.size());
-        BF_HIP(hipMemcpyAsync(P->tiles[l], t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice, s));
-        BF_HIP(hipStreamSynchronize(s));  // t is a host temporary
-    }
-    if (P->rho != 1.0) {
-        for (int m = 0; m < P->L; ++m) {
-            P->sig[m] = (double *)P->arena.alloc(sizeof(double) * 2 * P->d * P->tx.count[m]);
-            launch_sigma(P->tx.keys[m], P->tx.count[m], P->d, m, P->L, P->N, P->sig[m], s);
+    // clear the state once (a plan-time fill, never captured) so the timed
+    // arithmetic runs on finite values
+    const size_t bytes = state_bytes(P);
+    BF_HIP(hipMemsetAsync(P->buf[0], 0, bytes, P->stream));
+    BF_HIP(hipMemsetAsync(P->buf[1], 0, bytes, P->stream));
+    int best_kb = 0;
+    double best = 1e30;
+    for (int kb : {20, 24, 32, 40, 48}) {
+        build_tiles(P, kb * 1024);
+        const double ms = time_sweep(P, 2);
+        if (ms < best) {
+            best = ms;
+            best_kb = kb;
         }
     }
-    const size_t bytes = maxpairs * (size_t)P->PD * P->state_size;
-    P->buf[0] = P->arena.alloc(bytes);
-    P->buf[1] = P->arena.alloc(bytes);
-    BF_HIP(hipStreamSynchronize(s));
+    build_tiles(P, best_kb * 1024);
+    tune_store(key, {best_kb});
 }
 
 void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot)
@@ -211,21 +267,7 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
         launch_export(c, P->buf[0], P->tx.keys[0], 1, P->tk.keys[L], P->tk.count[L], L, L, P->N, pot);
     int cur = 0;
     for (int l = L - 1; l >= 0; --l) {
-        LevelArgs a;
-        a.in = P->buf[cur];
-        a.out = P->buf[cur ^ 1];
-        a.in_row = P->tk.count[l + 1];
-        a.out_row = P->tk.count[l];
-        a.x_cb = P->tx.child_beg[L - l - 1];
-        a.x_keys = P->tx.keys[L - l];
-        a.k_cb = P->tk.child_beg[l];
-        a.k_keys = P->tk.keys[l + 1];
-        a.tiles = P->tiles[l];
-        a.ntile = P->ntile[l];
-        a.cost_max = P->cost_max[l];
-        a.nap = P->tx.count[L - l - 1];
-        a.sig = P->sig[L - l - 1];
-        launch_translate(c, a);
+        launch_translate(c, level_args(P, l, P->buf[cur], P->buf[cur ^ 1]));
         if (ev) BF_HIP(hipEventRecord(ev[2 + (L - 1 - l)], P->stream));
         cur ^= 1;
         if (probe_level == l)
@@ -244,6 +286,135 @@ void free_events(bfsft_plan *P)
 }
 
 }  // namespace
+
+// Tiles, rows per work-group and LDS cost of every level for a tile budget.
+void build_tiles(bfsft_plan *P, int lds_bytes)
+{
+    P->lds = lds_bytes;
+    P->tiles.assign(P->L, nullptr);
+    P->ntile.assign(P->L, 0);
+    P->cost_max.assign(P->L, 0);
+    P->rows.assign(P->L, 1);
+    if (P->nx == 0 || P->nk == 0) return;
+    const int cap = translate_cap_blocks(P->d, P->p, P->precision, lds_bytes);
+    std::vector<int2> all;
+    std::vector<size_t> off(P->L);
+    for (int l = 0; l < P->L; ++l) {
+        const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
+        std::vector<int2> t = make_tiles(cb, P->d, cap);
+        off[l] = all.size();
+        P->ntile[l] = (int)t.size();
+        for (const int2 &b : t)
+            P->cost_max[l] = std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x));
+        P->rows[l] = translate_rows(cap, P->cost_max[l], P->tx.count[P->L - l - 1]);
+        all.insert(all.end(), t.begin(), t.end());
+    }
+    int2 *dev = (int2 *)P->arena.alloc(sizeof(int2) * all.size());
+    BF_HIP(hipMemcpyAsync(dev, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, P->stream));
+    BF_HIP(hipStreamSynchronize(P->stream));  // `all` is a host temporary
+    for (int l = 0; l < P->L; ++l) P->tiles[l] = dev + off[l];
+}
+
+void build_plan(bfsft_plan *P, const double *x, const double *k)
+{
+    hipStream_t s = P->stream;
+    if (validate_points(x, P->nx, P->d, P->N, s) || validate_points(k, P->nk, P->d, P->N, s))
+        throw Error{BFSFT_EDOMAIN, "a coordinate is not finite or lies outside [0, N]"};
+    build_tree(P->tx, x, P->nx, P->d, P->L, P->N, P->arena, s);
+    build_tree(P->tk, k, P->nk, P->d, P->L, P->N, P->arena, s);
+    build_tables(P->tb, P->p, P->N, P->L, P->arena, s);
+    P->sig.assign(P->L, nullptr);
+    if (P->nx == 0 || P->nk == 0) {
+        build_tiles(P, translate_default_lds());
+        BF_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    if (P->rho != 1.0) {
+        for (int m = 0; m < P->L; ++m) {
+            P->sig[m] = (double *)P->arena.alloc(sizeof(double) * 2 * P->d * P->tx.count[m]);
+            launch_sigma(P->tx.keys[m], P->tx.count[m], P->d, m, P->L, P->N, P->sig[m], s);
+        }
+    }
+    const size_t bytes = state_bytes(P);
+    P->buf[0] = P->arena.alloc(bytes);
+    P->buf[1] = P->arena.alloc(bytes);
+    build_tiles(P, translate_default_lds());
+    BF_HIP(hipStreamSynchronize(s));
+}
+
+void release_plan(bfsft_plan *P)
+{
+    (void)hipStreamSynchronize(P->stream);
+    free_events(P);
+    P->arena.release();
+}
+
+void run_single(bfsft_plan *P, const double *f, double *u) { run(P, f, u, -1, nullptr); }
+
+// ------------------------------------------------------------ tuning cache --
+
+bool autotune_enabled()
+{
+    const char *s = std::getenv("BFSFT_AUTOTUNE");
+    return !(s && s[0] == '0');
+}
+
+namespace {
+std::string tune_path()
+{
+    if (const char *s = std::getenv("BFSFT_TUNE_CACHE")) return s;
+    if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/bfsft_tune.txt";
+    return "";
+}
+
+std::string arch_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "gpu";
+    std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+}  // namespace
+
+bool tune_lookup(const std::string &key, std::vector<int> &vals)
+{
+    const std::string path = tune_path();
+    if (path.empty()) return false;
+    std::ifstream in(path);
+    std::string line;
+    const std::string full = arch_tag() + "/" + key;
+    bool found = false;
+    while (std::getline(in, line)) {  // the last entry for a key wins
+        std::istringstream ss(line);
+        std::string k;
+        ss >> k;
+        if (k != full) continue;
+        std::vector<int> v;
+        int x;
+        while (ss >> x) v.push_back(x);
+        if (!v.empty()) {
+            vals = v;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void tune_store(const std::string &key, const std::vector<int> &vals)
+{
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    std::ofstream out(path, std::ios::app);
+    if (!out) return;  // read-only or missing directory: tuning is simply not cached
+    out << arch_tag() << "/" << key;
+    for (int v : vals) out << " " << v;
+    out << "\n";
+}
+
+}  // namespace bfsft
+
+using namespace bfsft;
 
 extern "C" {
 
@@ -273,24 +444,14 @@ int bfsft_plan_create(bfsft_plan **out, int d, int64_t N, int p, int precision, 
     int rc = guarded([&] {
         check_scalars(d, N, p, precision, nx, nk, x, k);
         P = new bfsft_plan();
-        P->d = d;
-        P->p = p;
-        P->precision = precision;
-        P->N = N;
-        P->nx = nx;
-        P->nk = nk;
-        P->L = ceil_log2(N);
-        P->rho = std::ldexp((double)N, -P->L);
-        P->PD = d == 2 ? p * p : p * p * p;
-        P->stream = (hipStream_t)stream;
-        P->state_size = precision == BFSFT_FP64 ? 16 : 8;
-        P->arena.cap = env_cap();
+        init_plan(P, d, N, p, precision, nx, nk, (hipStream_t)stream);
         build_plan(P, x, k);
+        if (nx > 0 && nk > 0 && autotune_enabled()) autotune_single(P);
+        BF_HIP(hipStreamSynchronize(P->stream));
     });
     if (rc != BFSFT_OK) {
         if (P) {
-            (void)hipStreamSynchronize(P->stream);
-            P->arena.release();
+            release_plan(P);
             delete P;
         }
         return rc;
@@ -303,6 +464,7 @@ int bfsft_execute(bfsft_plan *plan, const double *f, double *u)
 {
     return guarded([&] {
         if (!plan) throw Error{BFSFT_EINVAL, "plan is NULL"};
+        if (plan->batched) throw Error{BFSFT_EINVAL, "batched plan: use bfsft_execute_batched"};
         if ((plan->nk > 0 && !f) || (plan->nx > 0 && !u)) throw Error{BFSFT_EINVAL, "NULL f or u"};
         if (plan->nx > 0 && plan->nk > 0 && (const void *)f == (const void *)u)
             throw Error{BFSFT_EINVAL, "u aliases f"};
@@ -313,7 +475,7 @@ int bfsft_execute(bfsft_plan *plan, const double *f, double *u)
 int bfsft_execute_probe(bfsft_plan *plan, const double *f, double *u, int level, double *pot)
 {
     return guarded([&] {
-        if (!plan) throw Error{BFSFT_EINVAL, "plan is NULL"};
+        if (!plan || plan->batched) throw Error{BFSFT_EINVAL, "plan is NULL or batched"};
         if (level < 0 || level > plan->L) throw Error{BFSFT_EINVAL, "level out of range"};
         if (!pot || !f || !u) throw Error{BFSFT_EINVAL, "NULL pointer"};
         if (plan->nx == 0 || plan->nk == 0) throw Error{BFSFT_EINVAL, "empty plan has no levels"};
@@ -324,7 +486,7 @@ int bfsft_execute_probe(bfsft_plan *plan, const double *f, double *u, int level,
 int bfsft_timing_begin(bfsft_plan *P, int max_execs)
 {
     return guarded([&] {
-        if (!P || max_execs < 1) throw Error{BFSFT_EINVAL, "bad timing request"};
+        if (!P || P->batched || max_execs < 1) throw Error{BFSFT_EINVAL, "bad timing request"};
         free_events(P);
         P->tev.resize((size_t)max_execs * (P->L + 3));
         for (auto &e : P->tev) BF_HIP(hipEventCreate(&e));
@@ -335,7 +497,7 @@ int bfsft_timing_begin(bfsft_plan *P, int max_execs)
 int bfsft_timing_end(bfsft_plan *P, double *out, int n)
 {
     return guarded([&] {
-        if (!P || !out || n < 3 + P->L) throw Error{BFSFT_EINVAL, "bad timing output"};
+        if (!P || P->batched || !out || n < 3 + P->L) throw Error{BFSFT_EINVAL, "bad timing output"};
         const int L = P->L;
         for (int i = 0; i < n; ++i) out[i] = 0.0;
         out[0] = P->tcount;
@@ -359,9 +521,10 @@ int bfsft_timing_end(bfsft_plan *P, double *out, int n)
 void bfsft_destroy(bfsft_plan *plan)
 {
     if (!plan) return;
-    (void)hipStreamSynchronize(plan->stream);
-    free_events(plan);
-    plan->arena.release();
+    if (plan->batched)
+        release_batched(plan);
+    else
+        release_plan(plan);
     delete plan;
 }
 
@@ -370,6 +533,10 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
     return guarded([&] {
         if (!P || !o) throw Error{BFSFT_EINVAL, "NULL argument"};
         std::memset(o, 0, sizeof(*o));
+        if (P->batched) {
+            info_batched(P, o);
+            return;
+        }
         o->d = P->d;
         o->p = P->p;
         o->precision = P->precision;
@@ -380,6 +547,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         o->rho = P->rho;
         o->transforms = 1;
         o->device_bytes = P->arena.bytes;
+        o->lds_kb = P->lds / 1024;
         if (P->nx == 0 || P->nk == 0) return;
         for (int m = 0; m <= P->L; ++m) {
             o->x_boxes[m] = P->tx.count[m];
@@ -400,7 +568,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
 int bfsft_plan_boxes(const bfsft_plan *P, int side, int m, int64_t *coords)
 {
     return guarded([&] {
-        if (!P || !coords) throw Error{BFSFT_EINVAL, "NULL argument"};
+        if (!P || !coords || P->batched) throw Error{BFSFT_EINVAL, "NULL argument or batched plan"};
         if (m < 0 || m > P->L || (side != 0 && side != 1)) throw Error{BFSFT_EINVAL, "bad side or level"};
         const Tree &t = side == 0 ? P->tx : P->tk;
         if (t.npts == 0) return;
@@ -417,23 +585,61 @@ int bfsft_plan_boxes(const bfsft_plan *P, int side, int m, int64_t *coords)
     });
 }
 
-int bfsft_plan_create_batched(bfsft_plan **out, int, const bfsft_problem *, int, int, int, void *)
+int bfsft_plan_create_batched(bfsft_plan **out, int count, const bfsft_problem *probs, int d, int p,
+                              int precision, void *stream)
 {
-    if (out) *out = nullptr;
-    set_last_error("batched plans are not available in this build");
-    return BFSFT_EINVAL;
+    if (!out) {
+        set_last_error("out is NULL");
+        return BFSFT_EINVAL;
+    }
+    *out = nullptr;
+    bfsft_plan *B = nullptr;
+    int rc = guarded([&] {
+        if (count < 1 || !probs) throw Error{BFSFT_EINVAL, "count < 1 or NULL problems"};
+        int64_t N0 = 2;
+        for (int t = 0; t < count; ++t) {
+            check_scalars(d, probs[t].N, p, precision, probs[t].nx, probs[t].nk, probs[t].x, probs[t].k);
+            N0 = std::max<int64_t>(N0, probs[t].N);
+        }
+        B = new bfsft_plan();
+        init_plan(B, d, N0, p, precision, 0, 0, (hipStream_t)stream);
+        B->batched = true;
+        for (int t = 0; t < count; ++t) {
+            bfsft_plan *S = new bfsft_plan();
+            B->subs.push_back(S);
+            init_plan(S, d, probs[t].N, p, precision, probs[t].nx, probs[t].nk, (hipStream_t)stream);
+            S->arena.cap = -1;  // the cap applies to the batched plan as a whole
+            build_plan(S, probs[t].x, probs[t].k);
+        }
+        create_batched(B, count, probs);
+    });
+    if (rc != BFSFT_OK) {
+        if (B) {
+            release_batched(B);
+            delete B;
+        }
+        return rc;
+    }
+    *out = B;
+    return BFSFT_OK;
 }
 
-int bfsft_execute_batched(bfsft_plan *, const double *, double *)
+int bfsft_execute_batched(bfsft_plan *B, const double *f, double *u)
 {
-    set_last_error("batched plans are not available in this build");
-    return BFSFT_EINVAL;
+    return guarded([&] {
+        if (!B || !B->batched) throw Error{BFSFT_EINVAL, "not a batched plan"};
+        if ((B->nk > 0 && !f) || (B->nx > 0 && !u)) throw Error{BFSFT_EINVAL, "NULL f or u"};
+        execute_batched(B, f, u, false);
+    });
 }
 
-int bfsft_execute_batched_serial(bfsft_plan *, const double *, double *)
+int bfsft_execute_batched_serial(bfsft_plan *B, const double *f, double *u)
 {
-    set_last_error("batched plans are not available in this build");
-    return BFSFT_EINVAL;
+    return guarded([&] {
+        if (!B || !B->batched) throw Error{BFSFT_EINVAL, "not a batched plan"};
+        if ((B->nk > 0 && !f) || (B->nx > 0 && !u)) throw Error{BFSFT_EINVAL, "NULL f or u"};
+        execute_batched(B, f, u, true);
+    });
 }
 
 }  // extern "C"

@@ -90,6 +90,7 @@ struct LevelArgs {
     const int2 *tiles;       // [ntile] b ranges
     int ntile;
     int cost_max;            // most LDS blocks any tile needs (translate_tile_cost)
+    int rows;                // rows a' per work-group
     int64_t nap;             // rows a'
     const double *sig;       // [nap][d] complex exp(2 pi i rho i_{A'}) or null (rho == 1)
 };
@@ -100,9 +101,45 @@ struct Launch {
     hipStream_t stream;
 };
 
-int translate_cap_blocks(int d, int p, int precision);
+int translate_default_lds();
+int translate_cap_blocks(int d, int p, int precision, int budget);
 int translate_tile_cost(int d, int nin, int nb);
 bool translate_fits(int d, int p, int precision);
+int translate_rows(int cap, int cost_max, int64_t nap);
+size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max);
+int64_t translate_items(const LevelArgs &la);
+size_t translate_desc_size();
+void translate_fill_desc(const Launch &c, const LevelArgs &la, void *dst);
+void launch_translate_batched(const Launch &c, const void *descs, const int64_t *prefix, int ndesc,
+                              int64_t total, size_t lds, int grid);
+
+// per-transform descriptors of the batched leaf and final launches; `first`
+// is the transform's first flat item
+struct LeafDesc {
+    const double *f;
+    const int32_t *perm;
+    const int32_t *beg;
+    const double *local;
+    void *state;
+    int64_t nleaf;
+    int64_t first;
+};
+
+struct FinalDesc {
+    const void *state;
+    const int32_t *leaf_of;
+    const double *local;
+    const double *bary;
+    const double *node_turns;
+    double *u;
+    int64_t nx;
+    int64_t first;
+};
+
+void launch_leaf_batched(const Launch &c, const LeafDesc *ds, const int64_t *prefix, int n,
+                         int64_t total);
+void launch_final_batched(const Launch &c, const FinalDesc *ds, const int64_t *prefix, int n,
+                          int64_t total);
 void launch_translate(const Launch &c, const LevelArgs &a);
 void launch_leaf(const Launch &c, const double *f, const Tree &tk, double rho, void *state);
 void launch_final(const Launch &c, const void *state, const Tree &tx, double rho, int64_t nx,

@@ -141,16 +141,14 @@ __global__ void k_sigma(const uint64_t *__restrict__ keys, int64_t n, int d, int
 // Step 2: w^{A0 B}_l = sum_{k_j in B} exp(2 pi i l . k'_j / q) f_j for every
 // leaf B of T_K (A0 = root of T_X).  One thread per (leaf, grid point).
 template <int D, typename S>
-__global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
-                                             const double2 *__restrict__ f,
-                                             const int32_t *__restrict__ perm,
-                                             const int32_t *__restrict__ beg,
-                                             const double *__restrict__ local,
-                                             typename CV<S>::t *__restrict__ state)
+__device__ __forceinline__ void leaf_item(int p, int64_t nleaf, const double2 *__restrict__ f,
+                                          const int32_t *__restrict__ perm,
+                                          const int32_t *__restrict__ beg,
+                                          const double *__restrict__ local,
+                                          typename CV<S>::t *__restrict__ state, int64_t gid)
 {
     int PD = p;
     for (int a = 1; a < D; ++a) PD *= p;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nleaf * PD) return;
     const int64_t b = gid / PD;
     const int e = (int)(gid - b * PD);
@@ -180,19 +178,52 @@ __global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
     state[gid] = o;
 }
 
+template <int D, typename S>
+__global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
+                                             const double2 *__restrict__ f,
+                                             const int32_t *__restrict__ perm,
+                                             const int32_t *__restrict__ beg,
+                                             const double *__restrict__ local,
+                                             typename CV<S>::t *__restrict__ state)
+{
+    leaf_item<D, S>(p, nleaf, f, perm, beg, local, state, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// index of the descriptor owning flat item `i` (prefix[t] <= i < prefix[t+1])
+__device__ __forceinline__ int owner(const int64_t *__restrict__ prefix, int n, int64_t i)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D, typename S>
+__global__ __launch_bounds__(256) void k_leaf_batched(int p, const LeafDesc *__restrict__ ds,
+                                                     const int64_t *__restrict__ prefix, int n,
+                                                     int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const LeafDesc &d = ds[owner(prefix, n, i)];
+    leaf_item<D, S>(p, d.nleaf, (const double2 *)d.f, d.perm, d.beg, d.local,
+                    (typename CV<S>::t *)d.state, i - d.first);
+}
+
 // ----------------------------------------------------------------- final --
 
 // Step 4: u_i = sum_l prod_a ell_{l_a}(exp(2 pi i x'_{i,a} / q)) w^{A B0}_l for
 // x_i in leaf A of T_X (barycentric Lagrange interpolation).
 template <int D, int P, typename S>
-__global__ __launch_bounds__(256) void k_final(int64_t nx, const typename CV<S>::t *__restrict__ state,
-                                              const int32_t *__restrict__ leaf_of,
-                                              const double *__restrict__ local,
-                                              const double2 *__restrict__ bary,
-                                              const double *__restrict__ node_turns,
-                                              double2 *__restrict__ u)
+__device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *__restrict__ state,
+                                           const int32_t *__restrict__ leaf_of,
+                                           const double *__restrict__ local,
+                                           const double2 *__restrict__ bary,
+                                           const double *__restrict__ node_turns,
+                                           double2 *__restrict__ u, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nx) return;
     constexpr int q = P - 1;
     double2 ell[D][P];
@@ -239,6 +270,30 @@ __global__ __launch_bounds__(256) void k_final(int64_t nx, const typename CV<S>:
         }
     }
     u[i] = acc;
+}
+
+template <int D, int P, typename S>
+__global__ __launch_bounds__(256) void k_final(int64_t nx, const typename CV<S>::t *__restrict__ state,
+                                              const int32_t *__restrict__ leaf_of,
+                                              const double *__restrict__ local,
+                                              const double2 *__restrict__ bary,
+                                              const double *__restrict__ node_turns,
+                                              double2 *__restrict__ u)
+{
+    final_item<D, P, S>(nx, state, leaf_of, local, bary, node_turns, u,
+                        (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int D, int P, typename S>
+__global__ __launch_bounds__(256) void k_final_batched(const FinalDesc *__restrict__ ds,
+                                                      const int64_t *__restrict__ prefix, int n,
+                                                      int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const FinalDesc &d = ds[owner(prefix, n, i)];
+    final_item<D, P, S>(d.nx, (const typename CV<S>::t *)d.state, d.leaf_of, d.local,
+                        (const double2 *)d.bary, d.node_turns, (double2 *)d.u, i - d.first);
 }
 
 // ----------------------------------------------------------------- export --
@@ -393,6 +448,43 @@ void launch_sigma(const uint64_t *keys, int64_t n, int d, int m, int L, int64_t 
 {
     if (n == 0) return;
     k_sigma<<<nblk(n, 256), 256, 0, s>>>(keys, n, d, m, L, N, (double2 *)sig);
+    BF_HIP(hipGetLastError());
+}
+
+void launch_leaf_batched(const Launch &c, const LeafDesc *ds, const int64_t *prefix, int n,
+                         int64_t total)
+{
+    if (total == 0) return;
+    const bool f32 = c.precision != BFSFT_FP64;
+    const int g = nblk(total, 256);
+    if (c.d == 2) {
+        if (f32) k_leaf_batched<2, float><<<g, 256, 0, c.stream>>>(c.p, ds, prefix, n, total);
+        else k_leaf_batched<2, double><<<g, 256, 0, c.stream>>>(c.p, ds, prefix, n, total);
+    } else {
+        if (f32) k_leaf_batched<3, float><<<g, 256, 0, c.stream>>>(c.p, ds, prefix, n, total);
+        else k_leaf_batched<3, double><<<g, 256, 0, c.stream>>>(c.p, ds, prefix, n, total);
+    }
+    BF_HIP(hipGetLastError());
+}
+
+void launch_final_batched(const Launch &c, const FinalDesc *ds, const int64_t *prefix, int n,
+                          int64_t total)
+{
+    if (total == 0) return;
+    const bool f32 = c.precision != BFSFT_FP64;
+    const int g = nblk(total, 256);
+    dispatch_p(c.p, [&](auto tag) {
+        constexpr int P = decltype(tag)::value;
+        if (c.d == 2) {
+            if (f32) k_final_batched<2, P, float><<<g, 256, 0, c.stream>>>(ds, prefix, n, total);
+            else k_final_batched<2, P, double><<<g, 256, 0, c.stream>>>(ds, prefix, n, total);
+        } else if constexpr (P <= 8) {
+            if (f32) k_final_batched<3, P, float><<<g, 256, 0, c.stream>>>(ds, prefix, n, total);
+            else k_final_batched<3, P, double><<<g, 256, 0, c.stream>>>(ds, prefix, n, total);
+        } else {
+            throw Error{BFSFT_EINVAL, "p > 8 in 3D"};
+        }
+    });
     BF_HIP(hipGetLastError());
 }
 

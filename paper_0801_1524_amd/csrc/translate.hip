@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 namespace bfsft {
@@ -39,7 +40,7 @@ namespace {
 constexpr int kTT = 256;       // threads of a translation work-group
 constexpr int kRowsMax = 32;   // rows a' per work-group
 constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
-constexpr size_t kLdsMax = 64 * 1024;  // dynamic LDS of one work-group
+constexpr size_t kLdsMax = 60 * 1024;  // dynamic LDS of one work-group (static use stays below 4 KB)
 
 struct TArgs {
     const void *in;
@@ -193,13 +194,12 @@ __device__ __forceinline__ void col_interp_s(cptr<C> Lt, cptr<C> PH, const typen
 //   stage 3 (axis 0): lines (b, m, n): out_t = sum over bit 0 of phase *
 //                     L_t0 along l, written to HBM.
 template <int P, bool RHO1, typename S, typename C>
-__global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
+__device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, unsigned char *smem)
 {
     using Sv = typename CV<S>::t;
     using Cv = typename CV<C>::t;
     using Yv = typename YT<S, C>::t;
     constexpr int P2 = P * P, P3 = P * P * P;
-    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_out[kRowsMax * 8];
     __shared__ int s_bits[kRowsMax];  // bit t: output t; bit 8+t2: some output with t2;
                                       // bit 16 + 2*t2 + t1: some output with (t1, t2)
@@ -207,7 +207,6 @@ __global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
     __shared__ unsigned char s_pos[kInMax];
     __shared__ signed char s_cj[kInMax * 8];
 
-    const int64_t gid = blockIdx.x;
     const int64_t g = gid / a.ntile;
     const int tile = (int)(gid - g * a.ntile);
     const int64_t ap0 = g * a.rows;
@@ -351,13 +350,12 @@ __global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
 
 
 template <int P, bool RHO1, typename S, typename C>
-__global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
+__device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, unsigned char *smem)
 {
     using Sv = typename CV<S>::t;
     using Cv = typename CV<C>::t;
     using Yv = typename YT<S, C>::t;
     constexpr int PP = P * P;
-    extern __shared__ __align__(16) unsigned char smem[];
     Yv *Y = reinterpret_cast<Yv *>(smem);  // [2 t2][R][nin][P][P]
     __shared__ int s_out[kRowsMax * 4];
     __shared__ int s_bits[kRowsMax];
@@ -365,7 +363,6 @@ __global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
     __shared__ unsigned char s_pos[kInMax];
     __shared__ signed char s_cj[kInMax * 4];  // [b][s]: local child index or -1
 
-    const int64_t gid = blockIdx.x;
     const int64_t g = gid / a.ntile;
     const int tile = (int)(gid - g * a.ntile);
     const int64_t ap0 = g * a.rows;
@@ -474,25 +471,63 @@ __global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
     }
 }
 
-int lds_budget()
+// One work item per work-group (single transform).
+template <int P, bool RHO1, typename S, typename C>
+__global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
 {
-    static int kb = [] {
-        const char *s = std::getenv("BFSFT_LDS_KB");
-        int v = s ? std::atoi(s) : 0;
-        return (v >= 8 && v <= 150) ? v : 40;
-    }();
-    return kb * 1024;
+    extern __shared__ __align__(16) unsigned char smem[];
+    translate2d_item<P, RHO1, S, C>(a, blockIdx.x, smem);
+}
+
+template <int P, bool RHO1, typename S, typename C>
+__global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    translate3d_item<P, RHO1, S, C>(a, blockIdx.x, smem);
+}
+
+// Persistent batched step: the work items of all transforms still active at
+// this sweep step form one index space (prefix[t] = first item of transform
+// t); each work-group walks it with stride gridDim.x until it is exhausted.
+template <int D, int P, typename S, typename C>
+__global__ __launch_bounds__(kTT) void k_translate_batched(const TArgs *__restrict__ descs,
+                                                          const int64_t *__restrict__ prefix,
+                                                          int ndesc, int64_t total)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        int lo = 0, hi = ndesc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        if constexpr (D == 2)
+            translate2d_item<P, false, S, C>(descs[lo], item - prefix[lo], smem);
+        else
+            translate3d_item<P, false, S, C>(descs[lo], item - prefix[lo], smem);
+        __syncthreads();  // the next item reuses the LDS
+    }
+}
+
+int lds_budget_default()
+{
+    const char *s = std::getenv("BFSFT_LDS_KB");
+    const int v = s ? std::atoi(s) : 0;
+    return ((v >= 8 && v <= 64) ? v : 32) * 1024;
 }
 
 }  // namespace
 
+int translate_default_lds() { return lds_budget_default(); }
+
 // LDS blocks (p^d elements of the intermediate type) a work-group may hold
-int translate_cap_blocks(int d, int p, int precision)
+// within `budget` bytes
+int translate_cap_blocks(int d, int p, int precision, int budget)
 {
     int PD = p;
     for (int a = 1; a < d; ++a) PD *= p;
     const int elem = precision == BFSFT_FP64 ? 16 : 8;
-    int cap = lds_budget() / (PD * elem);
+    int cap = budget / (PD * elem);
     const int one_box = d == 2 ? 2 * 4 : 8 + 2;  // a single box with all children
     if (cap < one_box) cap = one_box;
     return cap;
@@ -510,16 +545,17 @@ bool translate_fits(int d, int p, int precision)
     return (size_t)one_box * PD * elem <= kLdsMax;
 }
 
-int translate_rows(int d, int p, int precision, int cost_max, int64_t nap)
+int translate_rows(int cap, int cost_max, int64_t nap)
 {
-    int R = translate_cap_blocks(d, p, precision) / std::max(1, cost_max);
+    int R = cap / std::max(1, cost_max);
     R = std::max(1, std::min(R, kRowsMax));
     return (int)std::min<int64_t>(R, std::max<int64_t>(1, nap));
 }
 
-void launch_translate(const Launch &c, const LevelArgs &la)
+namespace {
+
+TArgs make_targs(const Launch &c, const LevelArgs &la)
 {
-    if (la.nap == 0 || la.ntile == 0) return;
     TArgs a;
     a.in = la.in;
     a.out = la.out;
@@ -532,22 +568,50 @@ void launch_translate(const Launch &c, const LevelArgs &la)
     a.tiles = la.tiles;
     a.ntile = la.ntile;
     a.nap = la.nap;
-    a.rows = translate_rows(c.d, c.p, c.precision, la.cost_max, la.nap);
+    a.rows = la.rows;
     a.sig = reinterpret_cast<const double2 *>(la.sig);
     const bool f32 = c.precision == BFSFT_FP32;
     a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
     a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
-    const int64_t groups = (la.nap + a.rows - 1) / a.rows;
-    const int64_t grid = groups * la.ntile;
+    return a;
+}
+
+size_t ysize(int precision) { return precision == BFSFT_FP64 ? 16 : 8; }
+
+}  // namespace
+
+size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max)
+{
+    size_t PD = (size_t)p * p * (d == 3 ? p : 1);
+    return (size_t)rows * cost_max * PD * ysize(precision);
+}
+
+int64_t translate_items(const LevelArgs &la)
+{
+    if (la.nap == 0 || la.ntile == 0) return 0;
+    return ((la.nap + la.rows - 1) / la.rows) * (int64_t)la.ntile;
+}
+
+size_t translate_desc_size() { return sizeof(TArgs); }
+
+void translate_fill_desc(const Launch &c, const LevelArgs &la, void *dst)
+{
+    const TArgs a = make_targs(c, la);
+    std::memcpy(dst, &a, sizeof(TArgs));
+}
+
+void launch_translate(const Launch &c, const LevelArgs &la)
+{
+    const int64_t grid = translate_items(la);
+    if (grid == 0) return;
+    const TArgs a = make_targs(c, la);
+    const size_t lds = translate_lds_bytes(c.d, c.p, c.precision, la.rows, la.cost_max);
+    if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
     auto body = [&](auto tag, auto *sp, auto *cp, auto d3) {
         constexpr int P = decltype(tag)::value;
         using S = std::remove_pointer_t<decltype(sp)>;
         using C = std::remove_pointer_t<decltype(cp)>;
-        constexpr bool D3 = decltype(d3)::value;
-        const size_t PD = D3 ? (size_t)P * P * P : (size_t)P * P;
-        const size_t lds = (size_t)a.rows * la.cost_max * PD * sizeof(typename YT<S, C>::t);
-        if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
-        if constexpr (D3) {
+        if constexpr (decltype(d3)::value) {
             if (la.sig)
                 k_translate3d<P, false, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
             else
@@ -559,15 +623,42 @@ void launch_translate(const Launch &c, const LevelArgs &la)
                 k_translate2d<P, true, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
         }
     };
-    if (c.d == 2) {
+    if (c.d == 2)
         dispatch_p(c.p, [&](auto tag) {
             dispatch_prec(c.precision, [&](auto *sp, auto *cp) { body(tag, sp, cp, std::false_type{}); });
         });
-    } else {
+    else
         dispatch_p3(c.p, [&](auto tag) {
             dispatch_prec(c.precision, [&](auto *sp, auto *cp) { body(tag, sp, cp, std::true_type{}); });
         });
-    }
+    BF_HIP(hipGetLastError());
+}
+
+void launch_translate_batched(const Launch &c, const void *descs, const int64_t *prefix, int ndesc,
+                              int64_t total, size_t lds, int grid)
+{
+    if (total == 0) return;
+    if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
+    const unsigned g = (unsigned)std::min<int64_t>(grid, total);
+    auto body = [&](auto tag, auto *sp, auto *cp, auto dd) {
+        constexpr int P = decltype(tag)::value;
+        constexpr int D = decltype(dd)::value;
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using C = std::remove_pointer_t<decltype(cp)>;
+        k_translate_batched<D, P, S, C><<<g, kTT, lds, c.stream>>>((const TArgs *)descs, prefix, ndesc, total);
+    };
+    if (c.d == 2)
+        dispatch_p(c.p, [&](auto tag) {
+            dispatch_prec(c.precision, [&](auto *sp, auto *cp) {
+                body(tag, sp, cp, std::integral_constant<int, 2>{});
+            });
+        });
+    else
+        dispatch_p3(c.p, [&](auto tag) {
+            dispatch_prec(c.precision, [&](auto *sp, auto *cp) {
+                body(tag, sp, cp, std::integral_constant<int, 3>{});
+            });
+        });
     BF_HIP(hipGetLastError());
 }
 
