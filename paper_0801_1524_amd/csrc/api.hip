@@ -190,44 +190,49 @@ size_t state_bytes(const bfsft_plan *P)
     return m * P->PD * P->state_size;
 }
 
-// Time one sweep (all levels) of a single plan, eagerly; best of `reps`
-// after one warm-up, milliseconds.
-double time_sweep(bfsft_plan *P, int reps)
+// Time one sweep of a single plan level by level, eagerly: ms[l] is the
+// best of `reps` runs (after one warm-up) of the launch producing T_K level l.
+std::vector<double> time_levels(bfsft_plan *P, int reps)
 {
     const Launch c = launch_of(P);
-    hipEvent_t e0, e1;
-    BF_HIP(hipEventCreate(&e0));
-    BF_HIP(hipEventCreate(&e1));
-    double best = 1e30;
+    const int L = P->L;
+    std::vector<hipEvent_t> ev(L + 1);
+    for (auto &e : ev) BF_HIP(hipEventCreate(&e));
+    std::vector<double> best(L, 1e30);
     for (int r = 0; r < reps + 1; ++r) {
-        BF_HIP(hipEventRecord(e0, P->stream));
+        BF_HIP(hipEventRecord(ev[0], P->stream));
         int cur = 0;
-        for (int l = P->L - 1; l >= 0; --l) {
+        for (int l = L - 1; l >= 0; --l) {
             launch_translate(c, level_args(P, l, P->buf[cur], P->buf[cur ^ 1]));
+            BF_HIP(hipEventRecord(ev[L - l], P->stream));
             cur ^= 1;
         }
-        BF_HIP(hipEventRecord(e1, P->stream));
-        BF_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        BF_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (r > 0) best = std::min(best, (double)ms);
+        BF_HIP(hipEventSynchronize(ev[L]));
+        if (r == 0) continue;
+        for (int i = 0; i < L; ++i) {
+            float ms = 0.f;
+            BF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            const int l = L - 1 - i;
+            best[l] = std::min(best[l], (double)ms);
+        }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto &e : ev) (void)hipEventDestroy(e);
     return best;
 }
 
-// Choose the tile LDS budget of a single plan by timing its sweep on its own
-// shapes.  The tiling does not change any result (every output is computed
-// by the same operations in the same order), only the speed.  Cached per
-// (architecture, d, p, precision, L).
+// Choose the tile LDS budget of every level of a single plan by timing the
+// sweep on the plan's own shapes.  The tiling does not change any result
+// (every output is computed by the same operations in the same order), only
+// the speed.  Cached per (architecture, d, p, precision, L).
 void autotune_single(bfsft_plan *P)
 {
     const std::string key = "single/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
                             prec_name(P->precision) + "/L" + std::to_string(P->L);
     std::vector<int> v;
-    if (tune_lookup(key, v) && v.size() == 1) {
-        build_tiles(P, v[0] * 1024);
+    if (tune_lookup(key, v) && (int)v.size() == P->L) {
+        std::vector<int> b(P->L);
+        for (int l = 0; l < P->L; ++l) b[l] = v[l] * 1024;
+        build_tiles_levels(P, b);
         return;
     }
     // clear the state once (a plan-time fill, never captured) so the timed
@@ -235,18 +240,22 @@ void autotune_single(bfsft_plan *P)
     const size_t bytes = state_bytes(P);
     BF_HIP(hipMemsetAsync(P->buf[0], 0, bytes, P->stream));
     BF_HIP(hipMemsetAsync(P->buf[1], 0, bytes, P->stream));
-    int best_kb = 0;
-    double best = 1e30;
-    for (int kb : {20, 24, 32, 40, 48}) {
+    const int cand[] = {16, 24, 32, 40, 48, 60};
+    std::vector<double> best(P->L, 1e30);
+    std::vector<int> pick(P->L, 32);
+    for (int kb : cand) {
         build_tiles(P, kb * 1024);
-        const double ms = time_sweep(P, 2);
-        if (ms < best) {
-            best = ms;
-            best_kb = kb;
-        }
+        const std::vector<double> ms = time_levels(P, 2);
+        for (int l = 0; l < P->L; ++l)
+            if (ms[l] < best[l]) {
+                best[l] = ms[l];
+                pick[l] = kb;
+            }
     }
-    build_tiles(P, best_kb * 1024);
-    tune_store(key, {best_kb});
+    std::vector<int> b(P->L);
+    for (int l = 0; l < P->L; ++l) b[l] = pick[l] * 1024;
+    build_tiles_levels(P, b);
+    tune_store(key, pick);
 }
 
 void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot)
@@ -287,19 +296,21 @@ void free_events(bfsft_plan *P)
 
 }  // namespace
 
-// Tiles, rows per work-group and LDS cost of every level for a tile budget.
-void build_tiles(bfsft_plan *P, int lds_bytes)
+// Tiles, rows per work-group and LDS cost of every level for per-level tile
+// budgets (bytes).
+void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes)
 {
-    P->lds = lds_bytes;
+    P->lds_level = lds_bytes;
+    P->lds = lds_bytes.empty() ? translate_default_lds() : lds_bytes[0];
     P->tiles.assign(P->L, nullptr);
     P->ntile.assign(P->L, 0);
     P->cost_max.assign(P->L, 0);
     P->rows.assign(P->L, 1);
     if (P->nx == 0 || P->nk == 0) return;
-    const int cap = translate_cap_blocks(P->d, P->p, P->precision, lds_bytes);
     std::vector<int2> all;
     std::vector<size_t> off(P->L);
     for (int l = 0; l < P->L; ++l) {
+        const int cap = translate_cap_blocks(P->d, P->p, P->precision, lds_bytes[l]);
         const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
         std::vector<int2> t = make_tiles(cb, P->d, cap);
         off[l] = all.size();
@@ -313,6 +324,11 @@ void build_tiles(bfsft_plan *P, int lds_bytes)
     BF_HIP(hipMemcpyAsync(dev, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, P->stream));
     BF_HIP(hipStreamSynchronize(P->stream));  // `all` is a host temporary
     for (int l = 0; l < P->L; ++l) P->tiles[l] = dev + off[l];
+}
+
+void build_tiles(bfsft_plan *P, int lds_bytes)
+{
+    build_tiles_levels(P, std::vector<int>(P->L, lds_bytes));
 }
 
 void build_plan(bfsft_plan *P, const double *x, const double *k)

@@ -66,6 +66,13 @@ template <int P, int T> struct Rows {
     static constexpr __host__ __device__ bool copy(int l) { return ((T * Q + l) & 1) == 0; }
     static constexpr int first_dot = (1 + T * Q) & 1;
     static constexpr int ndot = (P - first_dot + 1) / 2;
+    // position of copy row l among the copy rows
+    static constexpr __host__ __device__ int copy_index(int l)
+    {
+        int c = 0;
+        for (int i = 0; i < l; ++i) c += copy(i) ? 1 : 0;
+        return c;
+    }
 };
 
 // complex value of type Cv from an LDS/state element of another precision
@@ -150,6 +157,40 @@ __device__ __forceinline__ void col_interp(cptr<C> Lt, cptr<C> PH, const typenam
 }
 
 // (3D kernel below)
+// col_interp restricted to the output rows of group g of G: dot rows
+// k = g, g+G, ... and every G-th copy row.  g is uniform across the wave.
+template <int P, int T1, bool RHO1, typename S, typename C>
+__device__ __forceinline__ void col_interp_g(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *z0,
+                                             const typename CV<C>::t *z1, bool h1,
+                                             const typename CV<C>::t sg, typename CV<S>::t *dst,
+                                             int g, int G)
+{
+    using Cv = typename CV<C>::t;
+    using RW = Rows<P, T1>;
+    constexpr int PP = P * P, Q = P - 1;
+#pragma unroll 1
+    for (int k = g; k < RW::ndot; k += G) {
+        const int l = RW::first_dot + 2 * k;
+        Cv o0 = czero<Cv>(), o1 = czero<Cv>();
+#pragma unroll
+        for (int lp = 0; lp < P; ++lp) {
+            const Cv lv = ldc<Cv>(Lt, T1 * PP + l * P + lp);
+            cfma(o0, lv, z0[lp]);
+            cfma(o1, lv, z1[lp]);
+        }
+        if (h1) o0 = cadd(o0, cmul(o1, child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
+        st(dst + l * P, o0);
+    }
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        if (!RW::copy(l)) continue;
+        if (RW::copy_index(l) % G != g) continue;
+        Cv o = z0[(T1 * Q + l) / 2];
+        if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
+        st(dst + l * P, o);
+    }
+}
+
 // Y element type: the state precision for the FP32-state paths, FP64 otherwise
 template <typename S, typename C> struct YT { using t = typename CV<S>::t; };
 
@@ -404,69 +445,82 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     const cptr<C> Lt = (cptr<C>)(a.Lt);
     const cptr<C> PH = (cptr<C>)(a.PH);
     const int ysz = R * nin * PP;  // one t2 half of Y
+    int all = 0;
+    for (int r = 0; r < R; ++r) all |= s_bits[r];
 
-    // stage 1: every input row once, both output positions t2 it is needed for
-    for (int r = 0; r < R; ++r) {
-        const int bits = s_bits[r];  // uniform
-        const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * PP;
-        Yv *Yr = Y + r * nin * PP;
-        const Cv sg = s_sig[r * 2 + 1];
-        for (int v = threadIdx.x; v < nin * P; v += kTT) {
-            const int j = v / P;
-            const Sv *src = in + v * P;
-            Cv x[P];
+    // stage 1: every input row once, both output positions t2 it is needed
+    // for; the rows a' of the work-group are processed side by side
+    const int rowlen = nin * P;
+    for (int v = threadIdx.x; v < R * rowlen; v += kTT) {
+        const int r = v / rowlen;
+        const int w = v - r * rowlen;
+        const int j = w / P;
+        const int bits = s_bits[r];
+        const Sv *src = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * PP + w * P;
+        Cv x[P];
 #pragma unroll
-            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
-            const bool s2 = (s_pos[j] >> 1) & 1;
-            if (bits & (1 << 4)) row_interp<P, 0, RHO1, C>(Lt, PH, x, s2, sg, Yr + v * P);
-            if (bits & (1 << 5)) row_interp<P, 1, RHO1, C>(Lt, PH, x, s2, sg, Yr + ysz + v * P);
-        }
+        for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
+        const bool s2 = (s_pos[j] >> 1) & 1;
+        const Cv sg = s_sig[r * 2 + 1];
+        Yv *Yr = Y + r * nin * PP + w * P;
+        if (bits & (1 << 4)) row_interp<P, 0, RHO1, C>(Lt, PH, x, s2, sg, Yr);
+        if (bits & (1 << 5)) row_interp<P, 1, RHO1, C>(Lt, PH, x, s2, sg, Yr + ysz);
     }
     __syncthreads();
 
-    // stage 2: every output column once per t2, both output positions t1
-    for (int r = 0; r < R; ++r) {
-        const int bits = s_bits[r];
-        const Cv sg = s_sig[r * 2];
-        for (int t2 = 0; t2 < 2; ++t2) {
-            if (!(bits & (1 << (4 + t2)))) continue;  // uniform
+    // stage 2: every output column once per t2, both output positions t1,
+    // all rows side by side.  Narrow work splits the output rows over G
+    // wave-aligned groups of threads, so all four waves work.
+    const int ncol = nb * P;
+    const int ntot = R * ncol;
+    const int G = ntot <= 64 ? 4 : (ntot <= 128 ? 2 : 1);
+    const int span = kTT / G;
+    const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / span);
+    const int lane = (int)threadIdx.x - grp * span;
+    for (int t2 = 0; t2 < 2; ++t2) {
+        if (!(all & (1 << (4 + t2)))) continue;  // uniform
+        for (int v = lane; v < ntot; v += span) {
+            const int r = v / ncol;
+            const int col = v - r * ncol;
+            const int bits = s_bits[r];
+            if (!(bits & (1 << (4 + t2)))) continue;
+            const int bl = col / P, m = col - bl * P;
             const Yv *Yr = Y + t2 * ysz + r * nin * PP;
             const int a0 = s_out[r * 4 + (t2 << 1)], a1 = s_out[r * 4 + 1 + (t2 << 1)];
-            for (int v = threadIdx.x; v < nb * P; v += kTT) {
-                const int bl = v / P, m = v - bl * P;
-                const int c0 = s_cj[bl * 4 + 0], c2 = s_cj[bl * 4 + 2];
-                const int c1 = s_cj[bl * 4 + 1], c3 = s_cj[bl * 4 + 3];
-                Cv z0[P], z1[P];
+            const int c0 = s_cj[bl * 4 + 0], c2 = s_cj[bl * 4 + 2];
+            const int c1 = s_cj[bl * 4 + 1], c3 = s_cj[bl * 4 + 3];
+            // one branch per child slot, not per element
+            Cv z0[P], z1[P];
 #pragma unroll
-                for (int l = 0; l < P; ++l) z0[l] = z1[l] = czero<Cv>();
-                if (c0 >= 0) {
-                    const Yv *yp = Yr + c0 * PP + m;
+            for (int l = 0; l < P; ++l) z0[l] = z1[l] = czero<Cv>();
+            if (c0 >= 0) {
+                const Yv *yp = Yr + c0 * PP + m;
 #pragma unroll
-                    for (int l = 0; l < P; ++l) z0[l] = ld<Cv>(yp + l * P);
-                }
-                if (c2 >= 0) {
-                    const Yv *yp = Yr + c2 * PP + m;
-#pragma unroll
-                    for (int l = 0; l < P; ++l) z0[l] = cadd(z0[l], ld<Cv>(yp + l * P));
-                }
-                if (c1 >= 0) {
-                    const Yv *yp = Yr + c1 * PP + m;
-#pragma unroll
-                    for (int l = 0; l < P; ++l) z1[l] = ld<Cv>(yp + l * P);
-                }
-                if (c3 >= 0) {
-                    const Yv *yp = Yr + c3 * PP + m;
-#pragma unroll
-                    for (int l = 0; l < P; ++l) z1[l] = cadd(z1[l], ld<Cv>(yp + l * P));
-                }
-                const bool h1 = (c1 >= 0) | (c3 >= 0);
-                if (a0 >= 0)
-                    col_interp<P, 0, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
-                        reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m);
-                if (a1 >= 0)
-                    col_interp<P, 1, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
-                        reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m);
+                for (int l = 0; l < P; ++l) z0[l] = ld<Cv>(yp + l * P);
             }
+            if (c2 >= 0) {
+                const Yv *yp = Yr + c2 * PP + m;
+#pragma unroll
+                for (int l = 0; l < P; ++l) z0[l] = cadd(z0[l], ld<Cv>(yp + l * P));
+            }
+            if (c1 >= 0) {
+                const Yv *yp = Yr + c1 * PP + m;
+#pragma unroll
+                for (int l = 0; l < P; ++l) z1[l] = ld<Cv>(yp + l * P);
+            }
+            if (c3 >= 0) {
+                const Yv *yp = Yr + c3 * PP + m;
+#pragma unroll
+                for (int l = 0; l < P; ++l) z1[l] = cadd(z1[l], ld<Cv>(yp + l * P));
+            }
+            const bool h1 = (c1 >= 0) | (c3 >= 0);
+            const Cv sg = s_sig[r * 2];
+            if (a0 >= 0)
+                col_interp_g<P, 0, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
+                    reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m, grp, G);
+            if (a1 >= 0)
+                col_interp_g<P, 1, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
+                    reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m, grp, G);
         }
     }
 }
