@@ -144,6 +144,48 @@ def traffic_from_profile(precision):
     return ent.get("bytes_per_launch")
 
 
+def summarize_counters(fetch_dir, write_dir, precision, out_path):
+    """HBM traffic of the translation kernel from two rocprofv3 --pmc runs of
+    `bench.py --calib` (one with FETCH_SIZE, one with WRITE_SIZE).  Each
+    counter (KiB per dispatch) is scaled by what it reads for the 1 GiB
+    calibration copy, which moves exactly 2^30 bytes each way."""
+    import csv
+
+    def load(d, counter):
+        rows = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
+                if r["Counter_Name"] == counter]
+        tr = [float(r["Counter_Value"]) for r in rows if "k_translate" in r["Kernel_Name"]]
+        other = [float(r["Counter_Value"]) for r in rows if "bfsft" not in r["Kernel_Name"]]
+        return tr, max(other)
+
+    ftr, fcopy = load(fetch_dir, "FETCH_SIZE")
+    wtr, wcopy = load(write_dir, "WRITE_SIZE")
+    ff = (1 << 30) / (fcopy * 1024.0)
+    fw = (1 << 30) / (wcopy * 1024.0)
+    fetch = sum(ftr) / len(ftr) * 1024.0 * ff
+    write = sum(wtr) / len(wtr) * 1024.0 * fw
+    rec = {}
+    if os.path.exists(out_path):
+        try:
+            rec = json.load(open(out_path))
+        except ValueError:
+            rec = {}
+    if rec.get("kernel_sha") != kernel_hash():
+        rec = {"kernel_sha": kernel_hash(), "precisions": {}}
+    rec["precisions"][precision] = {
+        "bytes_per_launch": round(fetch + write), "fetch_bytes_per_launch": round(fetch),
+        "write_bytes_per_launch": round(write), "launches": len(ftr),
+        "calibration": {"fetch_factor": ff, "write_factor": fw},
+        "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- "
+                     f"python bench.py --precisions {precision} --steps 3 --warmup 1 --no-cpu --calib",
+                     f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- "
+                     f"python bench.py --precisions {precision} --steps 3 --warmup 1 --no-cpu --calib"],
+    }
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec["precisions"][precision]))
+
+
 def time_precision(bf, torch, P, precision, steps, warmup):
     plan = bf.Plan(P.d, P.N, P.p, P.x, P.k, precision)
     f = torch.from_numpy(P.f).to("cuda")
@@ -217,12 +259,18 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precisions", default="mixed,fp64,fp32")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the translation kernel's HBM traffic from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) to profiles/ and exit")
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"],
                     help="c2 (default) is the configuration the metric is quoted on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.precisions.split(",")[0], COUNTERS)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
               "described in DESIGN.md and not built", file=sys.stderr)
