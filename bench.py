@@ -207,6 +207,12 @@ def time_precision(bf, torch, P, precision, steps, warmup):
     ms = (t1 - t0) * 1e3 / steps
     log(f"[bench] {precision}: {ms:.3f} ms/step, translate {sum(tm['translate_ms'])/steps:.3f} ms, "
         f"leaf {tm['leaf_ms']/steps:.3f} ms, final {tm['final_ms']/steps:.3f} ms")
+    L = info["levels"]
+    log(f"[bench] {precision} per level l={L - 1}..0 (us): "
+        + " ".join(f"{1e3 * tm['translate_ms'][l] / steps:.0f}" for l in range(L - 1, -1, -1)))
+    log(f"[bench] {precision} kernel per level l={L - 1}..0: "
+        + "".join("m" if info["level_kernel"][L - 1 - i] else "v" for i in range(L))
+        + " lds_kb " + " ".join(str(info["level_lds_kb"][L - 1 - i]) for i in range(L)))
     return {"ms_per_step": ms, "timing": tm, "info": info, "u": out}
 
 

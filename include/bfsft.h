@@ -70,6 +70,9 @@ typedef struct {
     int64_t transforms;                   /* 1, or the count of a batched plan */
     int lds_kb;                           /* LDS budget of a translation tile (tuned) */
     int wg_per_cu;                        /* batched: persistent work-groups per CU (tuned) */
+    int level_kernel[BFSFT_MAX_LEVELS];   /* single plan, translation producing T_K level l:
+                                             0 VALU kernel, 1 matrix-core (MFMA) kernel */
+    int level_lds_kb[BFSFT_MAX_LEVELS];   /* single plan: tile LDS budget of level l (tuned) */
 } bfsft_info;
 
 /*
@@ -92,7 +95,10 @@ typedef struct {
  * Environment: BFSFT_MAX_DEVICE_BYTES caps the plan's device memory;
  * BFSFT_AUTOTUNE=0 disables the plan-time tuning of the translation tiles
  * (otherwise the sweep is timed on the plan's own shapes for a few tile LDS
- * budgets and the fastest is kept; results do not depend on the choice);
+ * budgets and, in 2D with 5 <= p <= 9 and FP64 arithmetic, for both the
+ * VALU and the matrix-core translation kernel, and the fastest is kept per
+ * level; results differ between the choices only by rounding);
+ * BFSFT_TRANSLATE=valu or =mfma restricts the kernel to one of the two;
  * BFSFT_TUNE_CACHE names the text file caching tuned choices (default
  * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget.
  */

@@ -99,6 +99,7 @@ LevelArgs level_args(const bfsft_plan *P, int l, const void *in, void *out)
     a.ntile = P->ntile[l];
     a.cost_max = P->cost_max[l];
     a.rows = P->rows[l];
+    a.kind = P->kind.empty() ? 0 : P->kind[l];
     a.nap = P->tx.count[L - l - 1];
     a.sig = P->sig[L - l - 1];
     return a;
@@ -109,15 +110,16 @@ namespace {
 // Tiles of T_K level l: ranges [b0, b1) whose LDS cost (translate_tile_cost
 // of their children count and size) is at most `cap`, with at most 120
 // children; a single box always fits, so every tile is non-empty.
-std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap)
+std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap, int kind)
 {
     std::vector<int2> t;
     const int n = (int)cb.size() - 1;
+    if (kind == 1) cap -= 1;  // the zero block of the matrix-core kernel
     int b0 = 0;
     while (b0 < n) {
         int b1 = b0 + 1;
         while (b1 < n && cb[b1 + 1] - cb[b0] <= 120 &&
-               translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0) <= cap)
+               translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0, kind) <= cap)
             ++b1;
         t.push_back(make_int2(b0, b1));
         b0 = b1;
@@ -220,19 +222,38 @@ std::vector<double> time_levels(bfsft_plan *P, int reps)
     return best;
 }
 
-// Choose the tile LDS budget of every level of a single plan by timing the
-// sweep on the plan's own shapes.  The tiling does not change any result
-// (every output is computed by the same operations in the same order), only
-// the speed.  Cached per (architecture, d, p, precision, L).
+// Kernels the tuner may use for this plan: bit 0 the VALU kernel, bit 1 the
+// matrix-core kernel; BFSFT_TRANSLATE=valu or =mfma restricts the choice.
+int kernel_choices(const bfsft_plan *P)
+{
+    int m = 1;
+    if (!P->valu_only && translate_mfma_supported(P->d, P->p, P->precision)) m |= 2;
+    if (const char *s = std::getenv("BFSFT_TRANSLATE")) {
+        if (std::strcmp(s, "valu") == 0) m &= 1;
+        else if (std::strcmp(s, "mfma") == 0 && (m & 2)) m = 2;
+    }
+    return m;
+}
+
+// Choose the kernel and the tile LDS budget of every level of a single plan
+// by timing the sweep on the plan's own shapes.  Neither changes what is
+// computed, only the order of the floating-point operations inside an
+// output and the speed.  Cached per (architecture, d, p, precision, L,
+// allowed kernels).
 void autotune_single(bfsft_plan *P)
 {
-    const std::string key = "single/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
-                            prec_name(P->precision) + "/L" + std::to_string(P->L);
+    const int choices = kernel_choices(P);
+    const std::string key = "single2/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
+                            prec_name(P->precision) + "/L" + std::to_string(P->L) + "/k" +
+                            std::to_string(choices);
     std::vector<int> v;
     if (tune_lookup(key, v) && (int)v.size() == P->L) {
-        std::vector<int> b(P->L);
-        for (int l = 0; l < P->L; ++l) b[l] = v[l] * 1024;
-        build_tiles_levels(P, b);
+        std::vector<int> b(P->L), k(P->L);
+        for (int l = 0; l < P->L; ++l) {
+            k[l] = v[l] / 100;
+            b[l] = (v[l] % 100) * 1024;
+        }
+        build_tiles_levels(P, b, k);
         return;
     }
     // clear the state once (a plan-time fill, never captured) so the timed
@@ -240,22 +261,29 @@ void autotune_single(bfsft_plan *P)
     const size_t bytes = state_bytes(P);
     BF_HIP(hipMemsetAsync(P->buf[0], 0, bytes, P->stream));
     BF_HIP(hipMemsetAsync(P->buf[1], 0, bytes, P->stream));
-    const int cand[] = {16, 24, 32, 40, 48, 60};
+    const int cand[] = {8, 12, 16, 24, 32, 40, 48, 60};
     std::vector<double> best(P->L, 1e30);
-    std::vector<int> pick(P->L, 32);
-    for (int kb : cand) {
-        build_tiles(P, kb * 1024);
-        const std::vector<double> ms = time_levels(P, 2);
-        for (int l = 0; l < P->L; ++l)
-            if (ms[l] < best[l]) {
-                best[l] = ms[l];
-                pick[l] = kb;
-            }
+    std::vector<int> pick(P->L, 32), pk(P->L, 0);
+    for (int kind = 0; kind < 2; ++kind) {
+        if (!(choices & (1 << kind))) continue;
+        for (int kb : cand) {
+            build_tiles_levels(P, std::vector<int>(P->L, kb * 1024), std::vector<int>(P->L, kind));
+            const std::vector<double> ms = time_levels(P, 2);
+            for (int l = 0; l < P->L; ++l)
+                if (ms[l] < best[l]) {
+                    best[l] = ms[l];
+                    pick[l] = kb;
+                    pk[l] = kind;
+                }
+        }
     }
-    std::vector<int> b(P->L);
-    for (int l = 0; l < P->L; ++l) b[l] = pick[l] * 1024;
-    build_tiles_levels(P, b);
-    tune_store(key, pick);
+    std::vector<int> b(P->L), store(P->L);
+    for (int l = 0; l < P->L; ++l) {
+        b[l] = pick[l] * 1024;
+        store[l] = pk[l] * 100 + pick[l];
+    }
+    build_tiles_levels(P, b, pk);
+    tune_store(key, store);
 }
 
 void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot)
@@ -298,9 +326,10 @@ void free_events(bfsft_plan *P)
 
 // Tiles, rows per work-group and LDS cost of every level for per-level tile
 // budgets (bytes).
-void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes)
+void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes, const std::vector<int> &kinds)
 {
     P->lds_level = lds_bytes;
+    P->kind = kinds.empty() ? std::vector<int>(P->L, 0) : kinds;
     P->lds = lds_bytes.empty() ? translate_default_lds() : lds_bytes[0];
     P->tiles.assign(P->L, nullptr);
     P->ntile.assign(P->L, 0);
@@ -312,12 +341,14 @@ void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes)
     for (int l = 0; l < P->L; ++l) {
         const int cap = translate_cap_blocks(P->d, P->p, P->precision, lds_bytes[l]);
         const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
-        std::vector<int2> t = make_tiles(cb, P->d, cap);
+        const int kind = P->kind[l];
+        std::vector<int2> t = make_tiles(cb, P->d, cap, kind);
         off[l] = all.size();
         P->ntile[l] = (int)t.size();
         for (const int2 &b : t)
-            P->cost_max[l] = std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x));
-        P->rows[l] = translate_rows(cap, P->cost_max[l], P->tx.count[P->L - l - 1]);
+            P->cost_max[l] =
+                std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x, kind));
+        P->rows[l] = translate_rows(cap, P->cost_max[l], P->tx.count[P->L - l - 1], kind);
         all.insert(all.end(), t.begin(), t.end());
     }
     int2 *dev = (int2 *)P->arena.alloc(sizeof(int2) * all.size());
@@ -328,7 +359,9 @@ void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes)
 
 void build_tiles(bfsft_plan *P, int lds_bytes)
 {
-    build_tiles_levels(P, std::vector<int>(P->L, lds_bytes));
+    // untuned: the VALU kernel unless BFSFT_TRANSLATE=mfma asks for the other
+    const int kind = kernel_choices(P) == 2 ? 1 : 0;
+    build_tiles_levels(P, std::vector<int>(P->L, lds_bytes), std::vector<int>(P->L, kind));
 }
 
 void build_plan(bfsft_plan *P, const double *x, const double *k)
@@ -564,6 +597,10 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         o->transforms = 1;
         o->device_bytes = P->arena.bytes;
         o->lds_kb = P->lds / 1024;
+        for (int l = 0; l < P->L && l < (int)P->kind.size(); ++l) {
+            o->level_kernel[l] = P->kind[l];
+            o->level_lds_kb[l] = P->lds_level[l] / 1024;
+        }
         if (P->nx == 0 || P->nk == 0) return;
         for (int m = 0; m <= P->L; ++m) {
             o->x_boxes[m] = P->tx.count[m];
@@ -624,6 +661,7 @@ int bfsft_plan_create_batched(bfsft_plan **out, int count, const bfsft_problem *
             bfsft_plan *S = new bfsft_plan();
             B->subs.push_back(S);
             init_plan(S, d, probs[t].N, p, precision, probs[t].nx, probs[t].nk, (hipStream_t)stream);
+            S->valu_only = true;
             S->arena.cap = -1;  // the cap applies to the batched plan as a whole
             build_plan(S, probs[t].x, probs[t].k);
         }

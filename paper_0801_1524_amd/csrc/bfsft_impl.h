@@ -70,9 +70,12 @@ struct Tables {
     float *L32 = nullptr;
     double *PH64 = nullptr;  // [2][p] complex: phase of a child at offset s = 1
     float *PH32 = nullptr;
+    double *LP64 = nullptr;  // [2][p][p] complex: PH_t[l] * L_t[l][l'] (rows of a child at s = 1)
+    float *LP32 = nullptr;
     double *nodes = nullptr; // [p] complex  Z_k (unused by kernels; kept for probes)
     double *bary = nullptr;  // [p] complex  barycentric weights of the nodes
     double *node_turns = nullptr; // [p] real  rho*k/q^2
+    double *mf = nullptr;    // per-lane operator tables of the matrix-core kernel (5 <= p <= 9)
 };
 
 void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t s);
@@ -91,6 +94,7 @@ struct LevelArgs {
     int ntile;
     int cost_max;            // most LDS blocks any tile needs (translate_tile_cost)
     int rows;                // rows a' per work-group
+    int kind;                // 0: VALU kernel, 1: matrix-core kernel (2D)
     int64_t nap;             // rows a'
     const double *sig;       // [nap][d] complex exp(2 pi i rho i_{A'}) or null (rho == 1)
 };
@@ -103,10 +107,10 @@ struct Launch {
 
 int translate_default_lds();
 int translate_cap_blocks(int d, int p, int precision, int budget);
-int translate_tile_cost(int d, int nin, int nb);
+int translate_tile_cost(int d, int nin, int nb, int kind = 0);
 bool translate_fits(int d, int p, int precision);
-int translate_rows(int cap, int cost_max, int64_t nap);
-size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max);
+int translate_rows(int cap, int cost_max, int64_t nap, int kind = 0);
+size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max, int kind = 0);
 int64_t translate_items(const LevelArgs &la);
 size_t translate_desc_size();
 void translate_fill_desc(const Launch &c, const LevelArgs &la, void *dst);
@@ -141,6 +145,12 @@ void launch_leaf_batched(const Launch &c, const LeafDesc *ds, const int64_t *pre
 void launch_final_batched(const Launch &c, const FinalDesc *ds, const int64_t *prefix, int n,
                           int64_t total);
 void launch_translate(const Launch &c, const LevelArgs &a);
+
+// matrix-core (MFMA) 2D translation with FP64 arithmetic (mixed and FP64)
+bool translate_mfma_supported(int d, int p, int precision);
+size_t translate_mfma_table_doubles(int p);
+void build_mfma_tables(const Tables &tb, int p, double *dst, hipStream_t s);
+void launch_translate_mfma(const Launch &c, const LevelArgs &la);
 void launch_leaf(const Launch &c, const double *f, const Tree &tk, double rho, void *state);
 void launch_final(const Launch &c, const void *state, const Tree &tx, double rho, int64_t nx,
                   double *u);

@@ -70,7 +70,8 @@ __device__ double2 diff_unit(double amb, double apb)
 // One thread block, FP64.  rho = N / 2^L; all turns are exact rationals
 // N n / (2 q^2 2^L) rounded once.
 __global__ void k_tables(int p, int64_t N, int L, double2 *L64, float2 *L32, double2 *PH64,
-                         float2 *PH32, double2 *nodes, double2 *bary, double *node_turns)
+                         float2 *PH32, double2 *LP64, float2 *LP32, double2 *nodes, double2 *bary,
+                         double *node_turns)
 {
     const int q = p - 1;
     const double den = ldexp(2.0 * q * q, L);  // 2 q^2 2^L
@@ -119,6 +120,11 @@ __global__ void k_tables(int p, int64_t N, int L, double2 *L64, float2 *L32, dou
         const double2 ph = expi_ratio(N * (int64_t)num, (int64_t)(2 * q) << L);
         PH64[t * p + l] = ph;
         PH32[t * p + l] = make_float2((float)ph.x, (float)ph.y);
+        for (int k = 0; k < p; ++k) {
+            const double2 v = dmul(ph, L64[(t * p + l) * p + k]);
+            LP64[(t * p + l) * p + k] = v;
+            LP32[(t * p + l) * p + k] = make_float2((float)v.x, (float)v.y);
+        }
     }
 }
 
@@ -354,13 +360,19 @@ void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t
     tb.L32 = (float *)arena.alloc(sizeof(float2) * 2 * p * p);
     tb.PH64 = (double *)arena.alloc(sizeof(double2) * 2 * p);
     tb.PH32 = (float *)arena.alloc(sizeof(float2) * 2 * p);
+    tb.LP64 = (double *)arena.alloc(sizeof(double2) * 2 * p * p);
+    tb.LP32 = (float *)arena.alloc(sizeof(float2) * 2 * p * p);
     tb.nodes = (double *)arena.alloc(sizeof(double2) * p);
     tb.bary = (double *)arena.alloc(sizeof(double2) * p);
     tb.node_turns = (double *)arena.alloc(sizeof(double) * p);
     k_tables<<<1, 64, 0, s>>>(p, N, L, (double2 *)tb.L64, (float2 *)tb.L32, (double2 *)tb.PH64,
-                              (float2 *)tb.PH32, (double2 *)tb.nodes, (double2 *)tb.bary,
-                              tb.node_turns);
+                              (float2 *)tb.PH32, (double2 *)tb.LP64, (float2 *)tb.LP32,
+                              (double2 *)tb.nodes, (double2 *)tb.bary, tb.node_turns);
     BF_HIP(hipGetLastError());
+    if (p >= 5 && p <= 9) {
+        tb.mf = (double *)arena.alloc(sizeof(double) * translate_mfma_table_doubles(p));
+        build_mfma_tables(tb, p, tb.mf, s);
+    }
 }
 
 void launch_leaf(const Launch &c, const double *f, const Tree &tk, double, void *state)

@@ -19,6 +19,8 @@ struct bfsft_plan {
     bfsft::Tables tb;
     int lds = 0;                        // LDS budget of a translation tile (bytes), most levels
     std::vector<int> lds_level;         // per T_K level l: tile LDS budget (bytes)
+    std::vector<int> kind;              // per T_K level l: 0 VALU kernel, 1 matrix-core kernel
+    bool valu_only = false;             // member of a batched plan (its kernel is the VALU one)
     std::vector<int2 *> tiles;          // per T_K level l = 0..L-1 (output level of the step)
     std::vector<int> ntile;
     std::vector<int> cost_max;          // most LDS blocks a tile of level l needs
@@ -63,7 +65,7 @@ namespace bfsft {
 Launch launch_of(const bfsft_plan *P);
 LevelArgs level_args(const bfsft_plan *P, int l, const void *in, void *out);
 void build_tiles(bfsft_plan *P, int lds_bytes);
-void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes);
+void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes, const std::vector<int> &kinds);
 void build_plan(bfsft_plan *P, const double *x, const double *k);
 void release_plan(bfsft_plan *P);
 int ceil_log2(int64_t N);

@@ -27,6 +27,7 @@
 #include "bfsft_impl.h"
 #include "cplx.h"
 #include "dispatch.h"
+#include "translate_common.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -37,57 +38,7 @@ namespace bfsft {
 
 namespace {
 
-constexpr int kTT = 256;       // threads of a translation work-group
-constexpr int kRowsMax = 32;   // rows a' per work-group
-constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
-constexpr size_t kLdsMax = 60 * 1024;  // dynamic LDS of one work-group (static use stays below 4 KB)
-
-struct TArgs {
-    const void *in;
-    void *out;
-    int64_t in_row, out_row;
-    const int32_t *x_cb;
-    const uint64_t *x_keys;
-    const int32_t *k_cb;
-    const uint64_t *k_keys;
-    const int2 *tiles;
-    int ntile;
-    int rows;
-    int64_t nap;
-    const double2 *sig;
-    const void *Lt;  // [2][P][P] complex, compute precision
-    const void *PH;  // [2][P] complex, compute precision
-};
-
-// Row structure of L_t: row l is the unit vector of node (t q + l) / 2 when
-// t q + l is even, a full interpolation row otherwise.
-template <int P, int T> struct Rows {
-    static constexpr int Q = P - 1;
-    static constexpr __host__ __device__ bool copy(int l) { return ((T * Q + l) & 1) == 0; }
-    static constexpr int first_dot = (1 + T * Q) & 1;
-    static constexpr int ndot = (P - first_dot + 1) / 2;
-    // position of copy row l among the copy rows
-    static constexpr __host__ __device__ int copy_index(int l)
-    {
-        int c = 0;
-        for (int i = 0; i < l; ++i) c += copy(i) ? 1 : 0;
-        return c;
-    }
-};
-
-// complex value of type Cv from an LDS/state element of another precision
-template <typename Cv, typename V> __device__ __forceinline__ Cv ld(const V *p)
-{
-    return cvt<Cv>(*p);
-}
-
-template <typename V, typename Cv> __device__ __forceinline__ void st(V *p, const Cv v)
-{
-    V o;
-    o.x = (decltype(o.x))v.x;
-    o.y = (decltype(o.y))v.y;
-    *p = o;
-}
+using namespace tr;
 
 // phase of a child at offset 1 along an axis, output index l, position t:
 // sigma_{A'} * PH_t[l]; sigma = 1 when rho = 1 (RHO1)
@@ -124,46 +75,16 @@ __device__ __forceinline__ void row_interp(cptr<C> Lt, cptr<C> PH, const typenam
     }
 }
 
-// stage 2 for one output column (z0: children with s1 = 0, z1: s1 = 1) and
-// output position T1 along axis 1
-template <int P, int T1, bool RHO1, typename S, typename C>
-__device__ __forceinline__ void col_interp(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *z0,
-                                           const typename CV<C>::t *z1, bool h1,
-                                           const typename CV<C>::t sg, typename CV<S>::t *dst)
-{
-    using Cv = typename CV<C>::t;
-    using RW = Rows<P, T1>;
-    constexpr int PP = P * P, Q = P - 1;
-#pragma unroll 1
-    for (int k = 0; k < RW::ndot; ++k) {
-        const int l = RW::first_dot + 2 * k;
-        Cv o0 = czero<Cv>(), o1 = czero<Cv>();
-#pragma unroll
-        for (int lp = 0; lp < P; ++lp) {
-            const Cv lv = ldc<Cv>(Lt, T1 * PP + l * P + lp);
-            cfma(o0, lv, z0[lp]);
-            cfma(o1, lv, z1[lp]);
-        }
-        if (h1) o0 = cadd(o0, cmul(o1, child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
-        st(dst + l * P, o0);
-    }
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-        if (!RW::copy(l)) continue;
-        Cv o = z0[(T1 * Q + l) / 2];
-        if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
-        st(dst + l * P, o);
-    }
-}
-
-// (3D kernel below)
-// col_interp restricted to the output rows of group g of G: dot rows
-// k = g, g+G, ... and every G-th copy row.  g is uniform across the wave.
-template <int P, int T1, bool RHO1, typename S, typename C>
-__device__ __forceinline__ void col_interp_g(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *z0,
+// Output column of stage 2 (2D) at position T1, restricted to the output
+// rows of group g of G (dot rows k = g, g+G, ... and every G-th copy row; g
+// is uniform across the wave).  z0 sums the children at s1 = 0, z1 those at
+// s1 = 1 with sigma_{A'} of axis 1 already applied, so the s1 = 1 rows use
+// the folded table LP = diag(PH_t) L_t and every dot row is one accumulator.
+template <int P, int T1, typename S, typename C>
+__device__ __forceinline__ void col_interp_g(cptr<C> Lt, cptr<C> LP, cptr<C> PH,
+                                             const typename CV<C>::t *z0,
                                              const typename CV<C>::t *z1, bool h1,
-                                             const typename CV<C>::t sg, typename CV<S>::t *dst,
-                                             int g, int G)
+                                             typename CV<S>::t *dst, int g, int G)
 {
     using Cv = typename CV<C>::t;
     using RW = Rows<P, T1>;
@@ -171,28 +92,30 @@ __device__ __forceinline__ void col_interp_g(cptr<C> Lt, cptr<C> PH, const typen
 #pragma unroll 1
     for (int k = g; k < RW::ndot; k += G) {
         const int l = RW::first_dot + 2 * k;
-        Cv o0 = czero<Cv>(), o1 = czero<Cv>();
+        Cv o = czero<Cv>();
 #pragma unroll
         for (int lp = 0; lp < P; ++lp) {
-            const Cv lv = ldc<Cv>(Lt, T1 * PP + l * P + lp);
-            cfma(o0, lv, z0[lp]);
-            cfma(o1, lv, z1[lp]);
+            cfma(o, ldc<Cv>(Lt, T1 * PP + l * P + lp), z0[lp]);
+            cfma(o, ldc<Cv>(LP, T1 * PP + l * P + lp), z1[lp]);
         }
-        if (h1) o0 = cadd(o0, cmul(o1, child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
-        st(dst + l * P, o0);
+        st(dst + l * P, o);
     }
 #pragma unroll
     for (int l = 0; l < P; ++l) {
         if (!RW::copy(l)) continue;
         if (RW::copy_index(l) % G != g) continue;
         Cv o = z0[(T1 * Q + l) / 2];
-        if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], child_phase<RHO1, Cv>(PH, T1, l, P, sg)));
+        if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], ldc<Cv>(PH, T1 * P + l)));
         st(dst + l * P, o);
     }
 }
 
 // Y element type: the state precision for the FP32-state paths, FP64 otherwise
+#ifdef BFSFT_MIXED_Y64
+template <typename S, typename C> struct YT { using t = typename CV<C>::t; };
+#else
 template <typename S, typename C> struct YT { using t = typename CV<S>::t; };
+#endif
 
 // Strided variant of col_interp: the output column has stride `stride`
 // elements and goes to a destination of element type Dv (LDS or HBM).
@@ -403,56 +326,23 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     __shared__ Cv s_sig[kRowsMax * 2];
     __shared__ unsigned char s_pos[kInMax];
     __shared__ signed char s_cj[kInMax * 4];  // [b][s]: local child index or -1
-
-    const int64_t g = gid / a.ntile;
-    const int tile = (int)(gid - g * a.ntile);
-    const int64_t ap0 = g * a.rows;
-    const int R = (int)min((int64_t)a.rows, a.nap - ap0);
-    const int2 bt = a.tiles[tile];
-    const int b0 = bt.x, nb = bt.y - bt.x;
-    const int J0 = a.k_cb[b0];
-    const int nin = a.k_cb[bt.y] - J0;
-
-    for (int i = threadIdx.x; i < nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[J0 + i] & 3);
-    for (int bl = threadIdx.x; bl < nb; bl += kTT) {
-        signed char cj[4] = {-1, -1, -1, -1};
-        for (int j = a.k_cb[b0 + bl]; j < a.k_cb[b0 + bl + 1]; ++j)
-            cj[a.k_keys[j] & 3] = (signed char)(j - J0);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) s_cj[bl * 4 + s] = cj[s];
-    }
-    if (threadIdx.x < R) {
-        const int r = threadIdx.x;
-        const int64_t ap = ap0 + r;
-        int bits = 0;
-        int o[4] = {-1, -1, -1, -1};
-        for (int i = a.x_cb[ap]; i < a.x_cb[ap + 1]; ++i) {
-            const int t = (int)(a.x_keys[i] & 3);
-            o[t] = i;
-            bits |= (1 << t) | (1 << (4 + (t >> 1)));
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) s_out[r * 4 + t] = o[t];
-        s_bits[r] = bits;
-        Cv one;
-        one.x = 1;
-        one.y = 0;
-        s_sig[r * 2] = a.sig ? cvt<Cv>(a.sig[ap * 2]) : one;
-        s_sig[r * 2 + 1] = a.sig ? cvt<Cv>(a.sig[ap * 2 + 1]) : one;
-    }
-    __syncthreads();
+    const Item2D it = setup2d<Cv>(a, gid, s_out, s_bits, s_sig, s_pos, s_cj);
+    const int64_t ap0 = it.ap0;
+    const int R = it.R, b0 = it.b0, nb = it.nb, J0 = it.J0, nin = it.nin, all = it.all;
 
     const cptr<C> Lt = (cptr<C>)(a.Lt);
     const cptr<C> PH = (cptr<C>)(a.PH);
+    const cptr<C> LP = (cptr<C>)(a.LP);
     const int ysz = R * nin * PP;  // one t2 half of Y
-    int all = 0;
-    for (int r = 0; r < R; ++r) all |= s_bits[r];
 
     // stage 1: every input row once, both output positions t2 it is needed
     // for; the rows a' of the work-group are processed side by side
+    // row a' of a flat index through a float reciprocal (exact: the index
+    // is below 2^16, so the error is far below the distance 0.5 / rowlen)
     const int rowlen = nin * P;
+    const float inv_rowlen = 1.0f / (float)rowlen;
     for (int v = threadIdx.x; v < R * rowlen; v += kTT) {
-        const int r = v / rowlen;
+        const int r = (int)(((float)v + 0.5f) * inv_rowlen);
         const int w = v - r * rowlen;
         const int j = w / P;
         const int bits = s_bits[r];
@@ -472,15 +362,16 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     // all rows side by side.  Narrow work splits the output rows over G
     // wave-aligned groups of threads, so all four waves work.
     const int ncol = nb * P;
+    const float inv_ncol = 1.0f / (float)ncol;
     const int ntot = R * ncol;
-    const int G = ntot <= 64 ? 4 : (ntot <= 128 ? 2 : 1);
+    const int G = (ntot <= 64 && kWaves >= 4) ? 4 : ((ntot <= 128 && kWaves >= 2) ? 2 : 1);
     const int span = kTT / G;
     const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / span);
     const int lane = (int)threadIdx.x - grp * span;
     for (int t2 = 0; t2 < 2; ++t2) {
         if (!(all & (1 << (4 + t2)))) continue;  // uniform
         for (int v = lane; v < ntot; v += span) {
-            const int r = v / ncol;
+            const int r = (int)(((float)v + 0.5f) * inv_ncol);
             const int col = v - r * ncol;
             const int bits = s_bits[r];
             if (!(bits & (1 << (4 + t2)))) continue;
@@ -514,20 +405,25 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
                 for (int l = 0; l < P; ++l) z1[l] = cadd(z1[l], ld<Cv>(yp + l * P));
             }
             const bool h1 = (c1 >= 0) | (c3 >= 0);
-            const Cv sg = s_sig[r * 2];
+            if (!RHO1 && h1) {
+                const Cv sg = s_sig[r * 2];
+#pragma unroll
+                for (int l = 0; l < P; ++l) z1[l] = cmul(sg, z1[l]);
+            }
             if (a0 >= 0)
-                col_interp_g<P, 0, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
+                col_interp_g<P, 0, S, C>(Lt, LP, PH, z0, z1, h1,
                     reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m, grp, G);
             if (a1 >= 0)
-                col_interp_g<P, 1, RHO1, S, C>(Lt, PH, z0, z1, h1, sg,
+                col_interp_g<P, 1, S, C>(Lt, LP, PH, z0, z1, h1,
                     reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m, grp, G);
         }
     }
 }
 
 // One work item per work-group (single transform).
+// at most 96 VGPRs: five waves per SIMD
 template <int P, bool RHO1, typename S, typename C>
-__global__ __launch_bounds__(kTT) void k_translate2d(TArgs a)
+__global__ __launch_bounds__(kTT, 5) void k_translate2d(TArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     translate2d_item<P, RHO1, S, C>(a, blockIdx.x, smem);
@@ -580,15 +476,25 @@ int translate_cap_blocks(int d, int p, int precision, int budget)
 {
     int PD = p;
     for (int a = 1; a < d; ++a) PD *= p;
+#ifdef BFSFT_MIXED_Y64
+    const int elem = precision != BFSFT_FP32 ? 16 : 8;
+#else
     const int elem = precision == BFSFT_FP64 ? 16 : 8;
+#endif
     int cap = budget / (PD * elem);
     const int one_box = d == 2 ? 2 * 4 : 8 + 2;  // a single box with all children
     if (cap < one_box) cap = one_box;
     return cap;
 }
 
-// LDS blocks a tile of nb boxes with nin children needs
-int translate_tile_cost(int d, int nin, int nb) { return d == 2 ? 2 * nin : nin + 2 * nb; }
+// LDS blocks a tile of nb boxes with nin children needs: the VALU kernels
+// hold the axis-2 results (2D: both t2) or two stages (3D); the matrix-core
+// kernel also stages the input blocks
+int translate_tile_cost(int d, int nin, int nb, int kind)
+{
+    if (kind == 1) return 3 * nin;
+    return d == 2 ? 2 * nin : nin + 2 * nb;
+}
 
 bool translate_fits(int d, int p, int precision)
 {
@@ -599,8 +505,9 @@ bool translate_fits(int d, int p, int precision)
     return (size_t)one_box * PD * elem <= kLdsMax;
 }
 
-int translate_rows(int cap, int cost_max, int64_t nap)
+int translate_rows(int cap, int cost_max, int64_t nap, int kind)
 {
+    if (kind == 1) cap -= 1;  // the zero block of absent children
     int R = cap / std::max(1, cost_max);
     R = std::max(1, std::min(R, kRowsMax));
     return (int)std::min<int64_t>(R, std::max<int64_t>(1, nap));
@@ -608,36 +515,18 @@ int translate_rows(int cap, int cost_max, int64_t nap)
 
 namespace {
 
-TArgs make_targs(const Launch &c, const LevelArgs &la)
-{
-    TArgs a;
-    a.in = la.in;
-    a.out = la.out;
-    a.in_row = la.in_row;
-    a.out_row = la.out_row;
-    a.x_cb = la.x_cb;
-    a.x_keys = la.x_keys;
-    a.k_cb = la.k_cb;
-    a.k_keys = la.k_keys;
-    a.tiles = la.tiles;
-    a.ntile = la.ntile;
-    a.nap = la.nap;
-    a.rows = la.rows;
-    a.sig = reinterpret_cast<const double2 *>(la.sig);
-    const bool f32 = c.precision == BFSFT_FP32;
-    a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
-    a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
-    return a;
-}
-
+#ifdef BFSFT_MIXED_Y64
+size_t ysize(int precision) { return precision != BFSFT_FP32 ? 16 : 8; }
+#else
 size_t ysize(int precision) { return precision == BFSFT_FP64 ? 16 : 8; }
+#endif
 
 }  // namespace
 
-size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max)
+size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max, int kind)
 {
     size_t PD = (size_t)p * p * (d == 3 ? p : 1);
-    return (size_t)rows * cost_max * PD * ysize(precision);
+    return ((size_t)rows * cost_max + (kind == 1 ? 1 : 0)) * PD * ysize(precision);
 }
 
 int64_t translate_items(const LevelArgs &la)
@@ -656,6 +545,10 @@ void translate_fill_desc(const Launch &c, const LevelArgs &la, void *dst)
 
 void launch_translate(const Launch &c, const LevelArgs &la)
 {
+    if (la.kind == 1) {
+        launch_translate_mfma(c, la);
+        return;
+    }
     const int64_t grid = translate_items(la);
     if (grid == 0) return;
     const TArgs a = make_targs(c, la);

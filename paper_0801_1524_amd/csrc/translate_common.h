@@ -1,0 +1,156 @@
+// Pieces shared by the two 2D/3D translation kernels of step 3 of
+// Section 2.2: the VALU kernels (translate.hip) and the matrix-core kernel
+// (translate_mfma.hip).  Internal to the library.
+#pragma once
+
+#include "bfsft_impl.h"
+#include "cplx.h"
+
+namespace bfsft {
+namespace tr {
+
+#ifndef BFSFT_TT
+#define BFSFT_TT 256
+#endif
+constexpr int kTT = BFSFT_TT;  // threads of a translation work-group
+constexpr int kWaves = kTT / 64;
+constexpr int kRowsMax = 32;   // rows a' per work-group
+constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
+constexpr size_t kLdsMax = 60 * 1024;  // dynamic LDS of one work-group (static use stays below 4 KB)
+
+struct TArgs {
+    const void *in;
+    void *out;
+    int64_t in_row, out_row;
+    const int32_t *x_cb;
+    const uint64_t *x_keys;
+    const int32_t *k_cb;
+    const uint64_t *k_keys;
+    const int2 *tiles;
+    int ntile;
+    int rows;
+    int64_t nap;
+    const double2 *sig;
+    const void *Lt;  // [2][P][P] complex, compute precision
+    const void *PH;  // [2][P] complex, compute precision
+    const void *LP;  // [2][P][P] complex, compute precision: PH_t[l] L_t[l][l']
+};
+
+inline TArgs make_targs(const Launch &c, const LevelArgs &la)
+{
+    TArgs a;
+    a.in = la.in;
+    a.out = la.out;
+    a.in_row = la.in_row;
+    a.out_row = la.out_row;
+    a.x_cb = la.x_cb;
+    a.x_keys = la.x_keys;
+    a.k_cb = la.k_cb;
+    a.k_keys = la.k_keys;
+    a.tiles = la.tiles;
+    a.ntile = la.ntile;
+    a.nap = la.nap;
+    a.rows = la.rows;
+    a.sig = reinterpret_cast<const double2 *>(la.sig);
+    const bool f32 = c.precision == BFSFT_FP32;
+    a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
+    a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
+    a.LP = f32 ? (const void *)c.tb->LP32 : (const void *)c.tb->LP64;
+    return a;
+}
+
+// Row structure of L_t: row l is the unit vector of node (t q + l) / 2 when
+// t q + l is even, a full interpolation row otherwise.
+template <int P, int T> struct Rows {
+    static constexpr int Q = P - 1;
+    static constexpr __host__ __device__ bool copy(int l) { return ((T * Q + l) & 1) == 0; }
+    static constexpr int first_dot = (1 + T * Q) & 1;
+    static constexpr int ndot = (P - first_dot + 1) / 2;
+    // position of copy row l among the copy rows
+    static constexpr __host__ __device__ int copy_index(int l)
+    {
+        int c = 0;
+        for (int i = 0; i < l; ++i) c += copy(i) ? 1 : 0;
+        return c;
+    }
+};
+
+// complex value of type Cv from an LDS/state element of another precision
+template <typename Cv, typename V> __device__ __forceinline__ Cv ld(const V *p)
+{
+    return cvt<Cv>(*p);
+}
+
+template <typename V, typename Cv> __device__ __forceinline__ void st(V *p, const Cv v)
+{
+    V o;
+    o.x = (decltype(o.x))v.x;
+    o.y = (decltype(o.y))v.y;
+    *p = o;
+}
+
+// Work item of a 2D translation work-group: R rows a' starting at ap0 and
+// the boxes [b0, b0 + nb) of T_K level l, whose nin children start at J0.
+struct Item2D {
+    int64_t ap0;
+    int R, b0, nb, J0, nin;
+    int all;  // union of the rows' output bits
+};
+
+// Per-work-group tables of a 2D item, filled cooperatively:
+//   s_out[r][t]   output row a of child t of row a' (or -1),
+//   s_bits[r]     bit t: child t present; bit 4 + t2: a child with that t2,
+//   s_sig[r][ax]  exp(2 pi i rho i_{A'}) per axis (1 when rho = 1),
+//   s_pos[j]      child position s of input j of the tile,
+//   s_cj[b][s]    local input index of child s of box b (or -1).
+template <typename Cv>
+__device__ __forceinline__ Item2D setup2d(const TArgs &a, int64_t gid, int *s_out, int *s_bits,
+                                          Cv *s_sig, unsigned char *s_pos, signed char *s_cj)
+{
+    Item2D it;
+    const int64_t g = gid / a.ntile;
+    const int tile = (int)(gid - g * a.ntile);
+    it.ap0 = g * a.rows;
+    it.R = (int)min((int64_t)a.rows, a.nap - it.ap0);
+    const int2 bt = a.tiles[tile];
+    it.b0 = bt.x;
+    it.nb = bt.y - bt.x;
+    it.J0 = a.k_cb[it.b0];
+    it.nin = a.k_cb[bt.y] - it.J0;
+    for (int i = threadIdx.x; i < it.nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[it.J0 + i] & 3);
+    for (int bl = threadIdx.x; bl < it.nb; bl += kTT) {
+        signed char cj[4] = {-1, -1, -1, -1};
+        for (int j = a.k_cb[it.b0 + bl]; j < a.k_cb[it.b0 + bl + 1]; ++j)
+            cj[a.k_keys[j] & 3] = (signed char)(j - it.J0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) s_cj[bl * 4 + s] = cj[s];
+    }
+    if ((int)threadIdx.x < it.R) {
+        const int r = threadIdx.x;
+        const int64_t ap = it.ap0 + r;
+        int bits = 0;
+        int o[4] = {-1, -1, -1, -1};
+        for (int i = a.x_cb[ap]; i < a.x_cb[ap + 1]; ++i) {
+            const int t = (int)(a.x_keys[i] & 3);
+            o[t] = i;
+            bits |= (1 << t) | (1 << (4 + (t >> 1)));
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) s_out[r * 4 + t] = o[t];
+        s_bits[r] = bits;
+        Cv one;
+        one.x = 1;
+        one.y = 0;
+        s_sig[r * 2] = a.sig ? cvt<Cv>(a.sig[ap * 2]) : one;
+        s_sig[r * 2 + 1] = a.sig ? cvt<Cv>(a.sig[ap * 2 + 1]) : one;
+    }
+    __syncthreads();
+    int all = 0;
+    for (int r = 0; r < it.R; ++r) all |= s_bits[r];
+    it.all = all;
+    return it;
+}
+
+}  // namespace tr
+
+}  // namespace bfsft

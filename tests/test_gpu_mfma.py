@@ -1,0 +1,123 @@
+"""The matrix-core (MFMA) 2D translation kernel, forced for every level with
+BFSFT_TRANSLATE=mfma, against the CPU oracle and against the VALU kernel.
+
+Bars: FP64 vs the oracle butterfly O2 rel-l2 <= 1e-10 (the two kernels
+compute the same operations in a different order, so only rounding
+differs); "mixed" vs O2 <= 2e-6 as for the VALU kernel; MFMA vs VALU at
+FP64 <= 1e-13.
+"""
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+from paper_0801_1524_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS = {5: 6e-3, 6: 1e-3, 7: 3e-4, 8: 2e-5, 9: 1.5e-6}
+
+
+@pytest.fixture(scope="module")
+def bf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_0801_1524_amd as bf
+    bf.lib()
+    return bf
+
+
+def run(bf, P, precision, kernel, monkeypatch, info=False):
+    monkeypatch.setenv("BFSFT_TRANSLATE", kernel)
+    with bf.Plan(P.d, P.N, P.p, P.x, P.k, precision) as plan:
+        u = plan.execute(P.f).cpu().numpy()
+        inf = plan.info()
+    want = 1 if kernel == "mfma" else 0
+    assert all(k == want for k in inf["level_kernel"]), inf["level_kernel"]
+    return (u, inf) if info else u
+
+
+def oracle_u(oracle_mod, P):
+    return oracle_mod.Butterfly(P.d, P.N, P.p, P.x, P.k).run(P.f)
+
+
+@pytest.mark.parametrize("p", [5, 6, 7, 8, 9])
+def test_mfma_every_p_fp64_vs_oracle(bf, oracle_mod, monkeypatch, p):
+    P = synth.curve_problem(512, p, seed=40 + p)
+    assert rel_l2(run(bf, P, "fp64", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mfma_c1_vs_oracle_and_direct(bf, oracle_mod, monkeypatch, precision):
+    P = synth.config("c1")
+    u = run(bf, P, precision, "mfma", monkeypatch)
+    assert rel_l2(u, oracle_u(oracle_mod, P)) <= {"fp64": 1e-10, "mixed": 2e-6}[precision]
+    S = synth.error_subset(P.nx, 1)
+    assert rel_l2(u[S], oracle_mod.direct(P.x, P.k, P.f, P.N, S)) <= EPS[P.p]
+
+
+@pytest.mark.parametrize("N,p", [(1000, 7), (3001, 9), (777, 5)])
+def test_mfma_non_power_of_two_N(bf, oracle_mod, monkeypatch, N, p):
+    # rho = N / 2^L < 1: the per-row phases sigma of both axes are applied
+    P = synth.curve_problem(N, p, seed=N)
+    assert rel_l2(run(bf, P, "fp64", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 1e-10
+
+
+@pytest.mark.parametrize("p", [7, 9])
+def test_mfma_matches_valu(bf, monkeypatch, p):
+    P = synth.curve_problem(4096, p, seed=60 + p)
+    u_m = run(bf, P, "fp64", "mfma", monkeypatch)
+    u_v = run(bf, P, "fp64", "valu", monkeypatch)
+    assert rel_l2(u_m, u_v) <= 1e-13
+    um = run(bf, P, "mixed", "mfma", monkeypatch)
+    uv = run(bf, P, "mixed", "valu", monkeypatch)
+    assert rel_l2(um, uv) <= 1e-6
+
+
+def test_mfma_level_potentials(bf, oracle_mod, monkeypatch):
+    P = synth.config("c1")
+    ob = oracle_mod.Butterfly(P.d, P.N, P.p, P.x, P.k)
+    monkeypatch.setenv("BFSFT_TRANSLATE", "mfma")
+    for lvl in (ob.L // 2, 0):
+        _, du, _ = ob.run(P.f, dump_level=lvl)
+        with bf.Plan(P.d, P.N, P.p, P.x, P.k, "fp64") as plan:
+            _, pot = plan.execute_probe(P.f, lvl)
+            pot = pot.cpu().numpy()
+            gx, gk = plan.boxes("x", ob.L - lvl), plan.boxes("k", lvl)
+        ox, ok = ob.boxes("x", ob.L - lvl), ob.boxes("k", lvl)
+        ix = {tuple(r): i for i, r in enumerate(ox)}
+        ik = {tuple(r): i for i, r in enumerate(ok)}
+        ref = du[np.array([ix[tuple(r)] for r in gx])][:, np.array([ik[tuple(r)] for r in gk])]
+        assert pot.shape == ref.shape
+        assert rel_l2(pot, ref) <= 1e-10
+
+
+def test_mfma_faces_clusters_single(bf, oracle_mod, monkeypatch):
+    N = 128
+    i = np.arange(N + 1, dtype=float)
+    x = np.stack([i, np.full(N + 1, float(N))], 1)
+    k = np.stack([np.zeros(N + 1), i], 1)
+    P = synth.Problem("faces", 2, N, 9, x, k, synth.gaussian_sources(N + 1, 8))
+    assert rel_l2(run(bf, P, "fp64", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 1e-10
+    rng = np.random.default_rng(3)
+    P = synth.Problem("cluster", 2, 256, 7, rng.uniform(100.0, 100.9, (50, 2)),
+                      rng.uniform(7.0, 7.5, (40, 2)), synth.gaussian_sources(40, 1))
+    assert rel_l2(run(bf, P, "fp64", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 1e-10
+    P = synth.Problem("one", 2, 64, 5, np.array([[3.25, 60.5]]), np.array([[17.0, 0.0]]),
+                      np.array([1.0 - 2.0j]))
+    assert rel_l2(run(bf, P, "mixed", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 2e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mfma_c2_full_size(bf, oracle_mod, monkeypatch, precision):
+    """N = 65536, p = 9: the 1e-6 gate on the error subset, and the oracle
+    restricted to 24 sampled targets (exactly their ancestor pairs)."""
+    c2 = synth.config("c2")
+    u = run(bf, c2, precision, "mfma", monkeypatch)
+    S = synth.error_subset(c2.nx, 2)
+    err = rel_l2(u[S], oracle_mod.direct(c2.x, c2.k, c2.f, c2.N, S))
+    assert err <= 1e-6, err
+    if precision == "fp64":
+        rng = np.random.default_rng(17)
+        T = np.sort(rng.choice(c2.nx, 24, replace=False))
+        ub = oracle_mod.Butterfly(c2.d, c2.N, c2.p, c2.x[T], c2.k).run(c2.f)
+        assert rel_l2(u[T], ub) <= 1e-10
