@@ -39,7 +39,7 @@ WORKLOADS = {
     "c3": "c3: 3D sparse FT, N=256, p=5, X = K = sphere r=0.4, Fibonacci lattice, 1 sample "
           "per unit area",
     "c4": "c4: 256 independent 2D transforms, N log-uniform in [512,16384], random ellipses, "
-          "p=7, one graph of persistent per-step launches",
+          "p=7, one graph with one launch per sweep step over all transforms",
 }
 
 

@@ -69,7 +69,8 @@ typedef struct {
     int64_t device_bytes;                 /* device memory owned by the plan */
     int64_t transforms;                   /* 1, or the count of a batched plan */
     int lds_kb;                           /* LDS budget of a translation tile (tuned) */
-    int wg_per_cu;                        /* batched: persistent work-groups per CU (tuned) */
+    int wg_per_cu;                        /* batched: persistent work-groups per CU (tuned); 0: one
+                                             work-group per work item instead */
     int level_kernel[BFSFT_MAX_LEVELS];   /* single plan, translation producing T_K level l:
                                              0 VALU kernel, 1 matrix-core (MFMA) kernel */
     int level_lds_kb[BFSFT_MAX_LEVELS];   /* single plan: tile LDS budget of level l (tuned) */

@@ -120,9 +120,13 @@ void build_leaf_final(bfsft_plan *B)
 void enqueue(bfsft_plan *B, hipStream_t s)
 {
     const Launch c = batch_launch(B, s);
+    // item counters of all steps start at zero (a kernel, not a memset node)
+    launch_zero_u64(B->step_next, (int64_t)B->steps.size(), s);
     launch_leaf_batched(c, B->leaf_desc, B->leaf_prefix, B->leaf_n, B->leaf_total);
-    for (const bfsft_plan::Step &st : B->steps)
-        launch_translate_batched(c, st.desc, st.prefix, st.ndesc, st.total, st.lds, B->grid);
+    for (size_t i = 0; i < B->steps.size(); ++i) {
+        const bfsft_plan::Step &st = B->steps[i];
+        launch_translate_batched(c, st.desc, st.prefix, st.ndesc, st.total, st.lds, B->grid, B->step_next + i);
+    }
     launch_final_batched(c, B->final_desc, B->final_prefix, B->final_n, B->final_total);
 }
 
@@ -134,9 +138,13 @@ double time_steps(bfsft_plan *B, int reps)
     BF_HIP(hipEventCreate(&e1));
     double best = 1e30;
     for (int r = 0; r < reps + 1; ++r) {
+        launch_zero_u64(B->step_next, (int64_t)B->steps.size(), B->stream);
         BF_HIP(hipEventRecord(e0, B->stream));
-        for (const bfsft_plan::Step &st : B->steps)
-            launch_translate_batched(c, st.desc, st.prefix, st.ndesc, st.total, st.lds, B->grid);
+        for (size_t i = 0; i < B->steps.size(); ++i) {
+            const bfsft_plan::Step &st = B->steps[i];
+            launch_translate_batched(c, st.desc, st.prefix, st.ndesc, st.total, st.lds, B->grid,
+                                     B->step_next + i);
+        }
         BF_HIP(hipEventRecord(e1, B->stream));
         BF_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -172,6 +180,7 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
     launch_zero_c128(B->u_stage, uo, B->stream);  // transforms without sources keep u = 0
     B->L = 0;
     for (bfsft_plan *S : B->subs) B->L = std::max(B->L, S->L);
+    B->step_next = (unsigned long long *)B->arena.alloc(sizeof(unsigned long long) * std::max(1, B->L));
 
     int dev = 0, ncu = 256;
     hipDeviceProp_t prop;
@@ -186,7 +195,7 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
 
     // autotuning: tile LDS budget x persistent work-groups per CU, timed on
     // the plan's own steps (results do not depend on either)
-    const std::string key = "batched/d" + std::to_string(B->d) + "/p" + std::to_string(B->p) + "/" +
+    const std::string key = "batched2/d" + std::to_string(B->d) + "/p" + std::to_string(B->p) + "/" +
                             prec_name(B->precision) + "/n" + std::to_string(count);
     std::vector<int> best;
     if (!tune_lookup(key, best) || best.size() != 2) {
@@ -198,10 +207,10 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
             for (size_t t = 0; t < B->subs.size(); ++t)
                 if (active(B->subs[t]))
                     run_single(B->subs[t], B->f_stage + 2 * B->f_off[t], B->u_stage + 2 * B->u_off[t]);
-            for (int kb : {20, 24, 32, 40}) {
+            for (int kb : {16, 20, 24, 32, 40}) {
                 for (bfsft_plan *S : B->subs) build_tiles(S, kb * 1024);
                 build_steps(B);
-                for (int wg : {2, 4, 8}) {
+                for (int wg : {0, 4, 5, 8}) {  // 0: one work-group per item
                     B->grid = ncu * wg;
                     const double ms = time_steps(B, 2);
                     if (ms < best_ms) {

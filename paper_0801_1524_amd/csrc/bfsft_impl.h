@@ -114,8 +114,9 @@ size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max, 
 int64_t translate_items(const LevelArgs &la);
 size_t translate_desc_size();
 void translate_fill_desc(const Launch &c, const LevelArgs &la, void *dst);
+// `next` is the step's item counter; it must be zero when the launch starts
 void launch_translate_batched(const Launch &c, const void *descs, const int64_t *prefix, int ndesc,
-                              int64_t total, size_t lds, int grid);
+                              int64_t total, size_t lds, int grid, unsigned long long *next);
 
 // per-transform descriptors of the batched leaf and final launches; `first`
 // is the transform's first flat item
@@ -157,6 +158,7 @@ void launch_final(const Launch &c, const void *state, const Tree &tx, double rho
 void launch_export(const Launch &c, const void *state, const uint64_t *xkeys, int64_t nA,
                    const uint64_t *kkeys, int64_t nB, int lvl, int L, int64_t N, double *pot);
 void launch_zero_c128(double *u, int64_t n, hipStream_t s);
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 void launch_sigma(const uint64_t *keys, int64_t n, int d, int m, int L, int64_t N,
                   double *sig, hipStream_t s);
 

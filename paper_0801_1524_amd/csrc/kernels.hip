@@ -344,6 +344,12 @@ __global__ void k_export(int d, int p, const typename CV<S>::t *__restrict__ st,
     pot[gid] = make_double2(c * w.x - s * w.y, c * w.y + s * w.x);
 }
 
+__global__ void k_zero_u64(unsigned long long *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ULL;
+}
+
 __global__ void k_zero_c128(double2 *u, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -445,6 +451,13 @@ void launch_export(const Launch &c, const void *state, const uint64_t *xkeys, in
     else
         k_export<float><<<nblk(n, 256), 256, 0, c.stream>>>(c.d, c.p, (const float2 *)state, xkeys,
                                                            nA, kkeys, nB, lvl, L, N, (double2 *)pot);
+    BF_HIP(hipGetLastError());
+}
+
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_zero_u64<<<nblk(n, 256), 256, 0, s>>>(p, n);
     BF_HIP(hipGetLastError());
 }
 

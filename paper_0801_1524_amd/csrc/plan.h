@@ -52,6 +52,7 @@ struct bfsft_plan {
     int64_t *final_prefix = nullptr;
     int final_n = 0;
     int64_t final_total = 0;
+    unsigned long long *step_next = nullptr;  // [steps] item counters of the step launches
     int grid = 0;                       // work-groups of a persistent step launch
     int wg_per_cu = 0;
     hipStream_t cap_stream = nullptr;

@@ -421,9 +421,12 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
 }
 
 // One work item per work-group (single transform).
-// at most 96 VGPRs: five waves per SIMD
+// Waves per SIMD the register allocation must allow: five (at most 96
+// VGPRs) up to p = 9; the larger grids of p >= 10 need the full register file.
+template <int D, int P> constexpr int min_waves() { return (D == 2 && P <= 9) ? 5 : 1; }
+
 template <int P, bool RHO1, typename S, typename C>
-__global__ __launch_bounds__(kTT, 5) void k_translate2d(TArgs a)
+__global__ __launch_bounds__(kTT, (min_waves<2, P>())) void k_translate2d(TArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     translate2d_item<P, RHO1, S, C>(a, blockIdx.x, smem);
@@ -438,25 +441,61 @@ __global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
 
 // Persistent batched step: the work items of all transforms still active at
 // this sweep step form one index space (prefix[t] = first item of transform
-// t); each work-group walks it with stride gridDim.x until it is exhausted.
+// t).  Work-groups take the next item from a counter that starts at zero
+// for every step, so late-starting work-groups cannot leave a tail; a
+// work-group finishes when the counter passes the end.
 template <int D, int P, typename S, typename C>
-__global__ __launch_bounds__(kTT) void k_translate_batched(const TArgs *__restrict__ descs,
-                                                          const int64_t *__restrict__ prefix,
-                                                          int ndesc, int64_t total)
+__global__ __launch_bounds__(kTT, (min_waves<D, P>() > 1 ? 4 : 1)) void k_translate_batched(
+    const TArgs *__restrict__ descs,
+                                                             const int64_t *__restrict__ prefix,
+                                                             int ndesc, int64_t total,
+                                                             unsigned long long *__restrict__ next)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    __shared__ int64_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(next, 1ULL);
+        __syncthreads();
+        // the item is the same for the whole work-group: keep it (and all
+        // that is derived from it) in scalar registers
+        const int64_t raw = s_item;
+        const int64_t item =
+            (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
+                      (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(raw & 0xffffffff)));
+        if (item >= total) break;
         int lo = 0, hi = ndesc - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
         }
+        const TArgs a = load_desc(descs, lo);
         if constexpr (D == 2)
-            translate2d_item<P, false, S, C>(descs[lo], item - prefix[lo], smem);
+            translate2d_item<P, false, S, C>(a, item - prefix[lo], smem);
         else
-            translate3d_item<P, false, S, C>(descs[lo], item - prefix[lo], smem);
-        __syncthreads();  // the next item reuses the LDS
+            translate3d_item<P, false, S, C>(a, item - prefix[lo], smem);
+        __syncthreads();  // the LDS and s_item are reused by the next item
     }
+}
+
+// The same step with one work-group per work item (the hardware scheduler
+// balances the items; no counter).
+template <int D, int P, typename S, typename C>
+__global__ __launch_bounds__(kTT, (min_waves<D, P>())) void k_translate_batched_flat(const TArgs *__restrict__ descs,
+                                                                  const int64_t *__restrict__ prefix,
+                                                                  int ndesc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t item = blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const TArgs a = load_desc(descs, lo);
+    if constexpr (D == 2)
+        translate2d_item<P, false, S, C>(a, item - prefix[lo], smem);
+    else
+        translate3d_item<P, false, S, C>(a, item - prefix[lo], smem);
 }
 
 int lds_budget_default()
@@ -582,7 +621,7 @@ void launch_translate(const Launch &c, const LevelArgs &la)
 }
 
 void launch_translate_batched(const Launch &c, const void *descs, const int64_t *prefix, int ndesc,
-                              int64_t total, size_t lds, int grid)
+                              int64_t total, size_t lds, int grid, unsigned long long *next)
 {
     if (total == 0) return;
     if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
@@ -592,7 +631,12 @@ void launch_translate_batched(const Launch &c, const void *descs, const int64_t 
         constexpr int D = decltype(dd)::value;
         using S = std::remove_pointer_t<decltype(sp)>;
         using C = std::remove_pointer_t<decltype(cp)>;
-        k_translate_batched<D, P, S, C><<<g, kTT, lds, c.stream>>>((const TArgs *)descs, prefix, ndesc, total);
+        if (grid <= 0)
+            k_translate_batched_flat<D, P, S, C><<<(unsigned)total, kTT, lds, c.stream>>>(
+                (const TArgs *)descs, prefix, ndesc);
+        else
+            k_translate_batched<D, P, S, C><<<g, kTT, lds, c.stream>>>((const TArgs *)descs, prefix, ndesc,
+                                                                       total, next);
     };
     if (c.d == 2)
         dispatch_p(c.p, [&](auto tag) {

@@ -36,6 +36,33 @@ struct TArgs {
     const void *LP;  // [2][P][P] complex, compute precision: PH_t[l] L_t[l][l']
 };
 
+// Descriptor i of a device array, read through the constant address space:
+// it is uniform and read-only, so every field becomes a scalar load (the
+// fields are copied one by one; the struct holds only pointers and integers)
+__device__ __forceinline__ TArgs load_desc(const TArgs *descs, int i)
+{
+    using CT = const __attribute__((address_space(4))) TArgs;
+    CT *d = (CT *)descs + i;
+    TArgs a;
+    a.in = d->in;
+    a.out = d->out;
+    a.in_row = d->in_row;
+    a.out_row = d->out_row;
+    a.x_cb = d->x_cb;
+    a.x_keys = d->x_keys;
+    a.k_cb = d->k_cb;
+    a.k_keys = d->k_keys;
+    a.tiles = d->tiles;
+    a.ntile = d->ntile;
+    a.rows = d->rows;
+    a.nap = d->nap;
+    a.sig = d->sig;
+    a.Lt = d->Lt;
+    a.PH = d->PH;
+    a.LP = d->LP;
+    return a;
+}
+
 inline TArgs make_targs(const Launch &c, const LevelArgs &la)
 {
     TArgs a;
