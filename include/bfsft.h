@@ -148,6 +148,21 @@ int bfsft_plan_boxes(const bfsft_plan *plan, int side, int m, int64_t *coords);
 int bfsft_execute_probe(bfsft_plan *plan, const double *f, double *u,
                         int level, double *pot);
 
+/*
+ * Adjoint transform (Section 1, eq. (1) with the roles of x and k exchanged
+ * and the sign of the phase reversed):
+ *     v_j = sum_i exp(-2 pi i x_i . k_j / N) g_i ,   j = 0 .. nk-1.
+ * The kernel of eq. (1) is symmetric in x and k, so this is the conjugate of
+ * the forward butterfly with T_X and T_K exchanged applied to conj(g); it
+ * shares the plan's trees and tables.
+ *   g  device, nx complex128 (interleaved), indexed like x.
+ *   v  device, nk complex128, overwritten; must not alias g.
+ * The first call on a plan builds the adjoint's tiles and state buffers
+ * (device allocation, tuning, stream synchronisation); later calls only
+ * enqueue work on the plan's stream.  nx = 0 gives v = 0.
+ */
+int bfsft_execute_adjoint(bfsft_plan *plan, const double *g, double *v);
+
 /* One problem of a batched plan (all points in device memory). */
 typedef struct {
     int64_t N;
@@ -158,9 +173,10 @@ typedef struct {
 /*
  * Batched plan: `count` independent transforms of the same d, p and
  * precision but their own N and points.  Execution runs sweep step
- * s = 1 .. max_t L_t for all transforms still active in one persistent launch
- * per step (transform t works on its T_K level L_t - s), all captured in one
- * HIP graph.
+ * s = 1 .. max_t L_t for all transforms still active in one launch per step
+ * (transform t works on its T_K level L_t - s; either one work-group per work
+ * item or persistent work-groups taking items from a counter, whichever the
+ * plan-time tuning found faster), all captured in one HIP graph.
  *   probs  host, [count] problem descriptors (device point pointers).
  * Sources and outputs are packed: transform t reads f_packed at offset
  * sum_{t'<t} nk_{t'} and writes u_packed at offset sum_{t'<t} nx_{t'}.

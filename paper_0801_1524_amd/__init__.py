@@ -65,6 +65,8 @@ def lib():
     L.bfsft_plan_create.restype = I
     L.bfsft_execute.argtypes = [P, P, P]
     L.bfsft_execute.restype = I
+    L.bfsft_execute_adjoint.argtypes = [P, P, P]
+    L.bfsft_execute_adjoint.restype = I
     L.bfsft_execute_probe.argtypes = [P, P, P, I, P]
     L.bfsft_execute_probe.restype = I
     L.bfsft_destroy.argtypes = [P]
@@ -180,6 +182,16 @@ class Plan:
         _check(self._L.bfsft_execute(self._h, ctypes.c_void_p(fd.data_ptr() if self.nk else 0),
                                      ctypes.c_void_p(u.data_ptr() if self.nx else 0)))
         return u
+
+    def execute_adjoint(self, g, out=None):
+        """v_j = sum_i exp(-2 pi i x_i . k_j / N) g_i (complex128 device tensor,
+        original source order) for values g at the targets."""
+        torch = _torch()
+        gd = _dev_complex(g, torch)
+        v = out if out is not None else torch.empty(self.nk, dtype=torch.complex128, device="cuda")
+        _check(self._L.bfsft_execute_adjoint(self._h, ctypes.c_void_p(gd.data_ptr() if self.nx else 0),
+                                             ctypes.c_void_p(v.data_ptr() if self.nk else 0)))
+        return v
 
     def execute_probe(self, f, level):
         """(u, pot): pot = check potentials u^{AB} of T_K level `level`,

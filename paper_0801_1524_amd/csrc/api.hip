@@ -394,8 +394,49 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
 void release_plan(bfsft_plan *P)
 {
     (void)hipStreamSynchronize(P->stream);
+    if (P->adj) {
+        release_plan(P->adj);  // its trees and tables belong to P
+        delete P->adj;
+        P->adj = nullptr;
+    }
     free_events(P);
     P->arena.release();
+}
+
+// The adjoint of a single plan: the same trees with the roles of x and k
+// exchanged (T_X of the adjoint is P's T_K and vice versa) and the same
+// tables; its own sigma tables, tiles, state buffers and input staging.
+bfsft_plan *make_adjoint(bfsft_plan *P)
+{
+    bfsft_plan *A = new bfsft_plan();
+    try {
+        init_plan(A, P->d, P->N, P->p, P->precision, P->nk, P->nx, P->stream);
+        A->arena.cap = P->arena.cap < 0 ? -1 : std::max<int64_t>(0, P->arena.cap - P->arena.bytes);
+        A->tx = P->tk;
+        A->tk = P->tx;
+        A->tb = P->tb;
+        A->sig.assign(A->L, nullptr);
+        A->adj_in = (double *)A->arena.alloc(sizeof(double) * 2 * std::max<int64_t>(1, A->nk));
+        if (A->nx > 0 && A->nk > 0) {
+            if (A->rho != 1.0)
+                for (int m = 0; m < A->L; ++m) {
+                    A->sig[m] = (double *)A->arena.alloc(sizeof(double) * 2 * A->d * A->tx.count[m]);
+                    launch_sigma(A->tx.keys[m], A->tx.count[m], A->d, m, A->L, A->N, A->sig[m], A->stream);
+                }
+            const size_t bytes = state_bytes(A);
+            A->buf[0] = A->arena.alloc(bytes);
+            A->buf[1] = A->arena.alloc(bytes);
+        }
+        build_tiles(A, translate_default_lds());
+        if (A->nx > 0 && A->nk > 0 && autotune_enabled()) autotune_single(A);
+        BF_HIP(hipStreamSynchronize(A->stream));
+    } catch (...) {
+        (void)hipStreamSynchronize(A->stream);
+        A->arena.release();
+        delete A;
+        throw;
+    }
+    return A;
 }
 
 void run_single(bfsft_plan *P, const double *f, double *u) { run(P, f, u, -1, nullptr); }
@@ -518,6 +559,23 @@ int bfsft_execute(bfsft_plan *plan, const double *f, double *u)
         if (plan->nx > 0 && plan->nk > 0 && (const void *)f == (const void *)u)
             throw Error{BFSFT_EINVAL, "u aliases f"};
         run(plan, f, u, -1, nullptr);
+    });
+}
+
+int bfsft_execute_adjoint(bfsft_plan *plan, const double *g, double *v)
+{
+    return guarded([&] {
+        if (!plan) throw Error{BFSFT_EINVAL, "plan is NULL"};
+        if (plan->batched) throw Error{BFSFT_EINVAL, "batched plans have no adjoint"};
+        if ((plan->nx > 0 && !g) || (plan->nk > 0 && !v)) throw Error{BFSFT_EINVAL, "NULL g or v"};
+        if (plan->nx > 0 && plan->nk > 0 && (const void *)g == (const void *)v)
+            throw Error{BFSFT_EINVAL, "v aliases g"};
+        if (plan->nk == 0) return;
+        if (!plan->adj) plan->adj = make_adjoint(plan);
+        bfsft_plan *A = plan->adj;
+        launch_conj(g, A->adj_in, plan->nx, plan->stream);
+        run(A, A->adj_in, v, -1, nullptr);
+        launch_conj(v, v, plan->nk, plan->stream);
     });
 }
 

@@ -159,6 +159,7 @@ void launch_export(const Launch &c, const void *state, const uint64_t *xkeys, in
                    const uint64_t *kkeys, int64_t nB, int lvl, int L, int64_t N, double *pot);
 void launch_zero_c128(double *u, int64_t n, hipStream_t s);
 void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
+void launch_conj(const double *in, double *out, int64_t n, hipStream_t s);  // out = conj(in), n complex
 void launch_sigma(const uint64_t *keys, int64_t n, int d, int m, int L, int64_t N,
                   double *sig, hipStream_t s);
 

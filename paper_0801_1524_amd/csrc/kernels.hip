@@ -350,6 +350,12 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t n)
     if (i < n) p[i] = 0ULL;
 }
 
+__global__ void k_conj(const double2 *__restrict__ in, double2 *__restrict__ out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_double2(in[i].x, -in[i].y);
+}
+
 __global__ void k_zero_c128(double2 *u, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,6 +464,13 @@ void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;
     k_zero_u64<<<nblk(n, 256), 256, 0, s>>>(p, n);
+    BF_HIP(hipGetLastError());
+}
+
+void launch_conj(const double *in, double *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_conj<<<nblk(n, 256), 256, 0, s>>>((const double2 *)in, (double2 *)out, n);
     BF_HIP(hipGetLastError());
 }
 

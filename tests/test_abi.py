@@ -27,7 +27,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for must in ("bfsft_plan_create", "bfsft_execute", "bfsft_destroy", "bfsft_strerror",
+    for must in ("bfsft_plan_create", "bfsft_execute", "bfsft_execute_adjoint", "bfsft_destroy", "bfsft_strerror",
                  "bfsft_plan_info", "bfsft_plan_create_batched", "bfsft_execute_batched"):
         assert must in names
 
@@ -70,3 +70,4 @@ def test_negative_count_and_null_points_rejected(lib):
 def test_execute_null_plan(lib):
     assert lib.bfsft_execute(None, None, None) == -1
     assert lib.bfsft_execute_batched(None, None, None) == -1
+    assert lib.bfsft_execute_adjoint(None, None, None) == -1
