@@ -63,7 +63,7 @@ def _load():
     lib.or_bf_matrix_M.restype = None
     lib.or_bf_matrix_E.argtypes = [P, I64, I64, P]
     lib.or_bf_matrix_E.restype = None
-    lib.or_bf_run.argtypes = [P, P, P, I, P, P]
+    lib.or_bf_run.argtypes = [P, P, P, I, P, P, I]
     lib.or_bf_run.restype = I
     lib.or_set_threads.argtypes = [I]
     lib.or_set_threads.restype = None
@@ -148,9 +148,11 @@ class Butterfly:
         self._lib.or_bf_matrix_E(self._h, int(iA), int(ic), _ptr(out))
         return out
 
-    def run(self, f, dump_level=None):
+    def run(self, f, dump_level=None, start_level=0):
         """Returns u (original target order); with dump_level, also the check
-        potentials and charges of that T_K level, shape (nA, nB, p^d)."""
+        potentials and charges of that T_K level, shape (nA, nB, p^d).
+        start_level s0: the sweep begins at T_K level L - s0 with charges
+        matched to directly summed potentials (0: at the leaves)."""
         f = np.ascontiguousarray(f, dtype=np.complex128)
         u = np.zeros(self.x.shape[0], dtype=np.complex128)
         du = df = None
@@ -163,7 +165,7 @@ class Butterfly:
             df = np.zeros_like(du)
         rc = self._lib.or_bf_run(self._h, _ptr(f), _ptr(u), lvl,
                                  _ptr(du) if du is not None else None,
-                                 _ptr(df) if df is not None else None)
+                                 _ptr(df) if df is not None else None, int(start_level))
         if rc != 0:
             raise RuntimeError(f"oracle butterfly failed ({rc})")
         if dump_level is None:

@@ -514,10 +514,17 @@ void or_bf_matrix_E(void *h, int64_t iA, int64_t ic, double *out)
  * (complex, original target order).  If dump_level is in [0, L], the check
  * potentials u^{AB} and charges f^{AB} of T_K level dump_level are copied to
  * dump_u / dump_f (layout [nA][nB][p^d], boxes in the order of or_bf_boxes;
- * A at T_X level L - dump_level).  Returns 0, or -1 on allocation failure.
+ * A at T_X level L - dump_level).
+ *
+ * start = s0 in [0, L] is the number of T_K levels above the leaves at
+ * which the sweep begins: the charges of the pairs (A at T_X level s0, B at
+ * T_K level L - s0) are matched to potentials summed directly over the
+ * sources in B (the plain procedure of Section 2.1), and step 3 continues
+ * from there.  s0 = 0 is step 2 of Section 2.2 (B a leaf, A the root).
+ * Returns 0, -1 on allocation failure, -3 for a bad start level.
  */
 int or_bf_run(void *h, const double *f_in, double *u_out, int dump_level,
-              double *dump_u, double *dump_f)
+              double *dump_u, double *dump_f, int start)
 {
     or_plan *P = h;
     const int d = P->d, p = P->p, q = P->q, L = P->L;
@@ -529,43 +536,72 @@ int or_bf_run(void *h, const double *f_in, double *u_out, int dump_level,
 
     for (int64_t i = 0; i < P->nx; ++i) u[i] = 0;
     if (P->nx == 0 || P->nk == 0) return 0;
+    if (start < 0 || start > L) return -3;
 
-    /* step 2: charges f^{A0 B} for every leaf B of T_K against the root A0 of
-     * T_X.  x^{A0}_l = l N / q per axis, so x^{A0}_l . k / N = sum_a l_a k_a / q. */
-    int64_t nB = P->tk[L].n;
-    cplx *cur = malloc(sizeof(cplx) * (size_t)nB * PD);
-    if (!cur) return -1;
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t b = 0; b < nB; ++b) {
-        cplx *X = cur + b * PD;
-        int64_t iB[3];
-        key_coords(P->tk[L].key[b], d, L, iB);
+    /* step 2 (at level l0 = L - s0): for every B at T_K level l0 and A at
+     * T_X level s0, u^{AB}_l = sum_{k_j in B} exp(2 pi i x^A_l . k_j / N) f_j
+     * with x^A_l = (i_A + l/q) N / 2^s0 per axis, so the phase of axis a is
+     * (q i_A + l) k_a / (q 2^s0) turns; then f^{AB} = M^{-1} u^{AB}. */
+    const int s0 = start, l0 = L - start;
+    const or_level *XS = &P->tx[s0], *KS = &P->tk[l0];
+    int64_t nAs = XS->n, nBs = KS->n;
+    cplx *cur = malloc(sizeof(cplx) * (size_t)nAs * nBs * PD);
+    /* sources of every box B of T_K level l0 (counting sort by box) */
+    int64_t *sbeg = calloc((size_t)nBs + 1, sizeof(int64_t));
+    int64_t *sidx = malloc(sizeof(int64_t) * (size_t)P->nk);
+    int64_t *sbox = malloc(sizeof(int64_t) * (size_t)P->nk);
+    if (!cur || !sbeg || !sidx || !sbox) { free(cur); free(sbeg); free(sidx); free(sbox); return -1; }
+    for (int64_t j = 0; j < P->nk; ++j) {
+        int64_t idx[3];
+        leaf_index(P->k + j * d, d, P->N, L, idx);
+        for (int a = 0; a < d; ++a) idx[a] >>= s0;
+        sbox[j] = find_box(KS, box_key(idx, d, l0));
+        sbeg[sbox[j] + 1]++;
+    }
+    for (int64_t b = 0; b < nBs; ++b) sbeg[b + 1] += sbeg[b];
+    {
+        int64_t *fill = malloc(sizeof(int64_t) * (size_t)nBs);
+        if (!fill) { free(cur); free(sbeg); free(sidx); free(sbox); return -1; }
+        memcpy(fill, sbeg, sizeof(int64_t) * (size_t)nBs);
+        for (int64_t j = 0; j < P->nk; ++j) sidx[fill[sbox[j]]++] = j;
+        free(fill);
+    }
+    free(sbox);
+    const double qs = (double)((int64_t)q << s0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t ab = 0; ab < nAs * nBs; ++ab) {
+        int64_t a = ab / nBs, b = ab % nBs;
+        cplx *X = cur + ab * PD;
+        int64_t iA[3], iB[3];
+        key_coords(XS->key[a], d, s0, iA);
+        key_coords(KS->key[b], d, l0, iB);
         for (int e = 0; e < PD; ++e) X[e] = 0;
-        for (int64_t t = P->kbeg[b]; t < P->kbeg[b + 1]; ++t) {
-            int64_t j = P->kperm[t];
+        for (int64_t t = sbeg[b]; t < sbeg[b + 1]; ++t) {
+            int64_t j = sidx[t];
             const double *kj = P->k + j * d;
             cplx ph[3][OR_PMAX];
-            for (int a = 0; a < d; ++a)
+            for (int s = 0; s < d; ++s)
                 for (int l = 0; l < p; ++l)
-                    ph[a][l] = expi_dd(dd_div(two_prod((double)l, kj[a]), (double)q));
+                    ph[s][l] = expi_dd(dd_div(two_prod((double)(q * iA[s] + l), kj[s]), qs));
             for (int e = 0; e < PD; ++e) {
                 cplx w = f[j];
                 int r = e;
-                for (int a = d - 1; a >= 0; --a) { w *= ph[a][r % p]; r /= p; }
+                for (int s = d - 1; s >= 0; --s) { w *= ph[s][r % p]; r /= p; }
                 X[e] += w;
             }
         }
-        if (dump_level == L && du)
-            for (int e = 0; e < PD; ++e) du[b * PD + e] = (dcplx)X[e];
-        int64_t iA[3] = {0, 0, 0};
+        if (dump_level == l0 && du)
+            for (int e = 0; e < PD; ++e) du[ab * PD + e] = (dcplx)X[e];
         solve_matching(P, iA, iB, X);
-        if (dump_level == L && df)
-            for (int e = 0; e < PD; ++e) df[b * PD + e] = (dcplx)X[e];
+        if (dump_level == l0 && df)
+            for (int e = 0; e < PD; ++e) df[ab * PD + e] = (dcplx)X[e];
     }
+    free(sbeg);
+    free(sidx);
 
-    /* step 3: for l = L-1 .. 0, every B at T_K level l and every A at T_X
+    /* step 3: for l = l0-1 .. 0, every B at T_K level l and every A at T_X
      * level L-l:  u^{AB} = sum_c E(A, B_c) f^{A' B_c},  f^{AB} = M^{-1} u^{AB}. */
-    for (int lvl = L - 1; lvl >= 0; --lvl) {
+    for (int lvl = l0 - 1; lvl >= 0; --lvl) {
         const or_level *XA = &P->tx[L - lvl], *XP = &P->tx[L - lvl - 1];
         const or_level *KB = &P->tk[lvl], *KC = &P->tk[lvl + 1];
         int64_t nA = XA->n, nBo = KB->n, nBc = KC->n;

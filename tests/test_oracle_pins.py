@@ -318,3 +318,71 @@ def test_trees_partition_points(oracle_mod):
         assert {tuple(r) for r in child >> 1} == parent
     leaf = np.minimum(np.floor(P.k * 2 ** B.L / P.N).astype(int), 2 ** B.L - 1)
     assert {tuple(r) for r in leaf} == {tuple(r) for r in B.boxes("k", B.L)}
+
+
+# ------------------------------------------------------ O2 start levels ---
+# The sweep may begin s0 levels above the leaves with potentials summed
+# directly over the sources of each box B (the plain procedure of
+# Section 2.1); s0 = 0 is the leaf start of Section 2.2.
+
+def _box_of(pts, N, L, lvl):
+    """box index of every point at level lvl (half-open boxes, x = N in the
+    last box), computed here from the coordinates"""
+    leaf = np.clip(np.floor(np.ldexp(pts, L) / N).astype(np.int64), 0, 2 ** L - 1)
+    return leaf >> (L - lvl)
+
+
+@pytest.mark.parametrize("s0", [1, 3, 5])
+def test_start_level_potentials_are_direct_sums(oracle_mod, s0):
+    """At level l0 = L - s0 the dumped check potentials equal O1 summed over
+    the sources in B, evaluated at A's Cartesian check points."""
+    P = synth.config("c1")
+    ob = oracle_mod.Butterfly(P.d, P.N, P.p, P.x, P.k)
+    L, q = ob.L, P.p - 1
+    l0 = L - s0
+    _, du, _ = ob.run(P.f, dump_level=l0, start_level=s0)
+    xa, kb = ob.boxes("x", s0), ob.boxes("k", l0)
+    kbox = _box_of(P.k, P.N, L, l0)
+    rng = np.random.default_rng(s0)
+    wA = P.N / 2 ** s0
+    grid = np.arange(P.p) * wA / q
+    for a, b in zip(rng.integers(0, len(xa), 6), rng.integers(0, len(kb), 6)):
+        inb = np.all(kbox == kb[b], axis=1)
+        c = xa[a] * wA
+        chk = np.array([[c[0] + g0, c[1] + g1] for g0 in grid for g1 in grid])
+        ref = oracle_mod.direct(chk, P.k[inb], P.f[inb], P.N)
+        assert rel_l2(du[a, b], ref) <= 1e-12, (a, b)
+
+
+@pytest.mark.parametrize("N,p", [(16, 5), (32, 7), (64, 9)])
+def test_start_level_brute_force_tiny(oracle_mod, N, p):
+    x = synth.circle(N, density=2.0)
+    k = synth.trefoil(N, density=2.0)
+    f = synth.gaussian_sources(len(k), N + p)
+    ob = oracle_mod.Butterfly(2, N, p, x, k)
+    ud = oracle_mod.direct(x, k, f, N)
+    for s0 in range(0, ob.L + 1):
+        assert rel_l2(ob.run(f, start_level=s0), ud) <= EPS_BOUND[p], s0
+
+
+def test_start_level_error_does_not_grow(oracle_mod):
+    """More of the field summed exactly never makes the result worse than
+    the leaf start by more than rounding (c1, p = 7)."""
+    P = synth.config("c1")
+    ob = oracle_mod.Butterfly(P.d, P.N, P.p, P.x, P.k)
+    S = synth.error_subset(P.nx, 1)
+    ud = oracle_mod.direct(P.x, P.k, P.f, P.N, S)
+    e0 = rel_l2(ob.run(P.f)[S], ud)
+    for s0 in (2, 4, 6):
+        assert rel_l2(ob.run(P.f, start_level=s0)[S], ud) <= 1.05 * e0
+
+
+def test_start_level_3d(oracle_mod):
+    N = 16
+    x = synth.sphere(N)
+    k = synth.sphere(N, radius=0.3)
+    f = synth.gaussian_sources(len(k), 2)
+    ob = oracle_mod.Butterfly(3, N, 5, x, k)
+    ud = oracle_mod.direct(x, k, f, N)
+    for s0 in (0, 1, 2, ob.L):
+        assert rel_l2(ob.run(f, start_level=s0), ud) <= EPS_BOUND[5], s0
