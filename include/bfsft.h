@@ -74,6 +74,8 @@ typedef struct {
     int level_kernel[BFSFT_MAX_LEVELS];   /* single plan, translation producing T_K level l:
                                              0 VALU kernel, 1 matrix-core (MFMA) kernel */
     int level_lds_kb[BFSFT_MAX_LEVELS];   /* single plan: tile LDS budget of level l (tuned) */
+    int start_level;                      /* single plan: the sweep starts at T_K level
+                                             levels - start_level (0: at the leaves) */
 } bfsft_info;
 
 /*
@@ -100,6 +102,12 @@ typedef struct {
  * VALU and the matrix-core translation kernel, and the fastest is kept per
  * level; results differ between the choices only by rounding);
  * BFSFT_TRANSLATE=valu or =mfma restricts the kernel to one of the two;
+ * the sweep starts start_level levels above the leaves of T_K, where the
+ * potentials of every pair are summed directly over the sources of B (the
+ * plain procedure of Section 2.1), with start_level chosen from the tree
+ * sizes by a fixed cost model (0 = the leaf start of Section 2.2) or forced
+ * by BFSFT_START_LEVEL=n (at most 18); results differ between start levels
+ * at the level of the method's error, not by rounding;
  * BFSFT_TUNE_CACHE names the text file caching tuned choices (default
  * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget.
  */

@@ -43,6 +43,7 @@ class Info(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("transforms", ctypes.c_int64),
         ("lds_kb", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
         ("level_kernel", ctypes.c_int * MAX_LEVELS), ("level_lds_kb", ctypes.c_int * MAX_LEVELS),
+        ("start_level", ctypes.c_int),
     ]
 
 
@@ -134,6 +135,7 @@ def _info_dict(info: Info) -> dict:
         "device_bytes": info.device_bytes, "transforms": info.transforms,
         "lds_kb": info.lds_kb, "wg_per_cu": info.wg_per_cu,
         "level_kernel": list(info.level_kernel[:L]), "level_lds_kb": list(info.level_lds_kb[:L]),
+        "start_level": info.start_level,
     }
 
 

@@ -297,13 +297,20 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
     const int L = P->L;
     hipEvent_t *ev = nullptr;
     if (P->tcount < P->tmax) ev = &P->tev[(size_t)P->tcount++ * (L + 3)];
+    const int s0 = P->start.s0, l0 = L - s0;
     if (ev) BF_HIP(hipEventRecord(ev[0], P->stream));
-    launch_leaf(c, f, P->tk, P->rho, P->buf[0]);
+    if (s0 == 0)
+        launch_leaf(c, f, P->tk, P->rho, P->buf[0]);
+    else
+        launch_direct(c, P->start, f, P->tx, P->tk, P->N, P->buf[0]);
     if (ev) BF_HIP(hipEventRecord(ev[1], P->stream));
-    if (probe_level == L)
-        launch_export(c, P->buf[0], P->tx.keys[0], 1, P->tk.keys[L], P->tk.count[L], L, L, P->N, pot);
+    if (probe_level == l0)
+        launch_export(c, P->buf[0], P->tx.keys[s0], P->tx.count[s0], P->tk.keys[l0], P->tk.count[l0], l0, L,
+                      P->N, pot);
+    if (ev)  // levels above the start have no translation: zero-length intervals
+        for (int l = L - 1; l >= l0; --l) BF_HIP(hipEventRecord(ev[2 + (L - 1 - l)], P->stream));
     int cur = 0;
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = l0 - 1; l >= 0; --l) {
         launch_translate(c, level_args(P, l, P->buf[cur], P->buf[cur ^ 1]));
         if (ev) BF_HIP(hipEventRecord(ev[2 + (L - 1 - l)], P->stream));
         cur ^= 1;
@@ -364,6 +371,49 @@ void build_tiles(bfsft_plan *P, int lds_bytes)
     build_tiles_levels(P, std::vector<int>(P->L, lds_bytes), std::vector<int>(P->L, kind));
 }
 
+// Start level of the sweep (the number of T_K levels above the leaves at
+// which potentials are summed directly), chosen from the tree counts alone so
+// that it never depends on timing: the s0 that minimises a cost model (ns on
+// one MI355X, constants fitted to the kernels' measured times)
+//   direct sums at level L - s0:  0.010 (1 + 0.15 (d - 2)) per pair, source and
+//                                 line of p^(d-1),
+//   translations below it:        (d = 2: 6.4e-4, d = 3: 1.54e-3) p^(d+1) per pair,
+//   leaf initialisation (s0 = 0): 5.7e-3 per source and grid point.
+// A start above the leaves is taken only if it saves at least 3 % of the
+// modelled time.  BFSFT_START_LEVEL=n forces n (clamped to [0, min(L, kStartMax)]).
+int choose_start(const bfsft_plan *P)
+{
+    if (P->nx == 0 || P->nk == 0 || P->valu_only) return 0;
+    const int L = P->L, d = P->d;
+    if (const char *e = std::getenv("BFSFT_START_LEVEL")) {
+        char *end = nullptr;
+        const long v = std::strtol(e, &end, 10);
+        if (end != e) return (int)std::max(0L, std::min((long)std::min(L, kStartMax), v));
+    }
+    const double p = P->p;
+    const double lines = d == 2 ? p : p * p;
+    auto pairs = [&](int l) { return (double)P->tx.count[L - l] * (double)P->tk.count[l]; };
+    const double tr = (d == 2 ? 6.4e-4 : 1.54e-3) * std::pow(p, d + 1);
+    const double dr = 0.010 * (1.0 + 0.15 * (d - 2));
+    std::vector<double> below(L + 1, 0.0);  // below[l0]: translations producing levels < l0
+    for (int l = 1; l <= L; ++l) below[l] = below[l - 1] + tr * pairs(l - 1);
+    const double leaf_cost = 5.7e-3 * (double)P->nk * std::pow(p, d) + below[L];
+    int best = 0;
+    double best_cost = leaf_cost;
+    for (int s = 1; s <= std::min(L, kStartMax); ++s) {
+        const int l0 = L - s;
+        const double per_box = (double)P->nk / (double)P->tk.count[l0];
+        const double cost = dr * pairs(l0) * per_box * lines + below[l0];
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = s;
+        }
+    }
+    // the leaf start of the paper unless the model predicts a clear gain
+    // (it is within a few per cent of the measured times)
+    return best_cost < 0.97 * leaf_cost ? best : 0;
+}
+
 void build_plan(bfsft_plan *P, const double *x, const double *k)
 {
     hipStream_t s = P->stream;
@@ -387,6 +437,7 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     const size_t bytes = state_bytes(P);
     P->buf[0] = P->arena.alloc(bytes);
     P->buf[1] = P->arena.alloc(bytes);
+    build_start(P->start, P->tk, choose_start(P), P->d, P->p - 1, P->rho, P->arena, s);
     build_tiles(P, translate_default_lds());
     BF_HIP(hipStreamSynchronize(s));
 }
@@ -426,6 +477,7 @@ bfsft_plan *make_adjoint(bfsft_plan *P)
             const size_t bytes = state_bytes(A);
             A->buf[0] = A->arena.alloc(bytes);
             A->buf[1] = A->arena.alloc(bytes);
+            build_start(A->start, A->tk, choose_start(A), A->d, A->p - 1, A->rho, A->arena, A->stream);
         }
         build_tiles(A, translate_default_lds());
         if (A->nx > 0 && A->nk > 0 && autotune_enabled()) autotune_single(A);
@@ -583,7 +635,8 @@ int bfsft_execute_probe(bfsft_plan *plan, const double *f, double *u, int level,
 {
     return guarded([&] {
         if (!plan || plan->batched) throw Error{BFSFT_EINVAL, "plan is NULL or batched"};
-        if (level < 0 || level > plan->L) throw Error{BFSFT_EINVAL, "level out of range"};
+        if (level < 0 || level > plan->L - plan->start.s0)
+            throw Error{BFSFT_EINVAL, "level out of range (above the start level there are no potentials)"};
         if (!pot || !f || !u) throw Error{BFSFT_EINVAL, "NULL pointer"};
         if (plan->nx == 0 || plan->nk == 0) throw Error{BFSFT_EINVAL, "empty plan has no levels"};
         run(plan, f, u, level, pot);
@@ -655,6 +708,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         o->transforms = 1;
         o->device_bytes = P->arena.bytes;
         o->lds_kb = P->lds / 1024;
+        o->start_level = P->start.s0;
         for (int l = 0; l < P->L && l < (int)P->kind.size(); ++l) {
             o->level_kernel[l] = P->kind[l];
             o->level_lds_kb[l] = P->lds_level[l] / 1024;

@@ -147,6 +147,20 @@ void launch_final_batched(const Launch &c, const FinalDesc *ds, const int64_t *p
                           int64_t total);
 void launch_translate(const Launch &c, const LevelArgs &a);
 
+// Start of the sweep s0 levels above the leaves (s0 = 0: the leaves).
+struct StartLevel {
+    int s0 = 0;
+    int2 *box_leaf = nullptr;   // [count_K[L - s0]] leaf range of every box of T_K level L - s0
+    int32_t *sm = nullptr;      // [npts][d] leaf index mod 2^s0 of every source (sorted order)
+    double *sloc = nullptr;     // [npts][d] offset inside its leaf (sorted order)
+    double2 *sratio = nullptr;  // [npts] phase step of the last axis between grid points
+};
+// s0 <= 18 keeps the exact phase reduction of the direct sums in 64-bit integers
+constexpr int kStartMax = 18;
+void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rho, Arena &arena, hipStream_t s);
+void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
+                   int64_t N, void *state);
+
 // matrix-core (MFMA) 2D translation with FP64 arithmetic (mixed and FP64)
 bool translate_mfma_supported(int d, int p, int precision);
 size_t translate_mfma_table_doubles(int p);

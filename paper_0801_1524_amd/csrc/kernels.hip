@@ -195,6 +195,136 @@ __global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
     leaf_item<D, S>(p, nleaf, f, perm, beg, local, state, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// ---------------------------------------------------------- start level --
+// The sweep may begin s0 levels above the leaves: the twisted check
+// potentials of every pair (A at T_X level s0, B at T_K level L - s0) are
+// summed directly over the sources in B (the plain procedure of
+// Section 2.1):
+//     w^{AB}_l = sum_{k_j in B} exp(2 pi i x^A_l . (k_j - c^B) / N) f_j,
+//     x^A_l = (i_A + l / q) N / 2^s0 per axis,
+// so the phase of axis a is (q i_A + l) (k_j - c^B)_a / (q 2^s0) turns.
+// Each offset k_j - c^B = rho m + loc is stored split: m = leaf index mod
+// 2^s0 (an integer), loc = offset inside the leaf (exact).
+
+// offsets of the sources, in the trees' sorted order
+// and the phase step of the last axis, exp(2 pi i (rho m + loc) / (q 2^s0))
+template <int D>
+__global__ void k_source_offsets(int64_t n, int s0, int q, double rho, const int32_t *__restrict__ perm,
+                                 const int32_t *__restrict__ leaf_of, const uint64_t *__restrict__ leaf_keys,
+                                 const double *__restrict__ local, int32_t *__restrict__ sm,
+                                 double *__restrict__ sloc, double2 *__restrict__ sratio)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int j = perm[t];
+    const uint64_t key = leaf_keys[leaf_of[j]];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        int m = 0;
+        for (int b = 0; b < s0; ++b) m |= (int)((key >> (b * D + a)) & 1) << b;
+        sm[t * D + a] = m;
+        sloc[t * D + a] = local[(int64_t)j * D + a];
+        if (a == D - 1) {
+            double sn, cs;
+            sincospi(2.0 * (rho * m + local[(int64_t)j * D + a]) / ldexp((double)q, s0), &sn, &cs);
+            sratio[t] = make_double2(cs, sn);
+        }
+    }
+}
+
+// turns of (q i_A + l) (rho m + loc) / (q 2^s0) modulo 1 (up to one extra
+// turn): the rho m part is the exact rational X / (q 2^E) with
+// X = (q i_A + l) m N and E = s0 + L, reduced in integers as
+// X mod q 2^E = ((X >> E) mod q) 2^E + (X mod 2^E)  (X < 2^64 for s0 <= 18,
+// q a compile-time constant); the loc part is below two turns, in FP64
+template <int Q>
+__device__ __forceinline__ double direct_turns(int64_t qil, int m, double loc, int E, double inv_den,
+                                               double inv_qs, int64_t N)
+{
+    const uint64_t X = (uint64_t)(qil * (int64_t)m) * (uint64_t)N;
+    const uint64_t r = (((X >> E) % (uint64_t)Q) << E) | (X & ((1ull << E) - 1ull));
+    return (double)r * inv_den + (double)qil * loc * inv_qs;
+}
+
+__device__ __forceinline__ double2 expi_turns(double t)
+{
+    double s, c;
+    sincospi(2.0 * t, &s, &c);
+    return make_double2(c, s);
+}
+
+// one thread per (pair, line): a line fixes the grid indices of the leading
+// d - 1 axes; the p values along the last axis use a phase recurrence
+template <int D, int P, typename S>
+__global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_t nA, int64_t nB,
+                                               const uint64_t *__restrict__ xkeys,
+                                               const int2 *__restrict__ box_leaf,
+                                               const int32_t *__restrict__ leaf_beg,
+                                               const int32_t *__restrict__ perm,
+                                               const int32_t *__restrict__ sm,
+                                               const double *__restrict__ sloc,
+                                               const double2 *__restrict__ sratio,
+                                               const double2 *__restrict__ f,
+                                               typename CV<S>::t *__restrict__ state)
+{
+    constexpr int Q = P - 1;
+    constexpr int PL = D == 2 ? P : P * P;  // lines per pair
+    constexpr int PD = PL * P;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nA * nB * PL) return;
+    const int64_t ab = gid / PL;
+    const int line = (int)(gid - ab * PL);
+    const int64_t a = ab / nB, b = ab - a * nB;
+    int64_t iA[3] = {0, 0, 0};
+    {
+        const uint64_t key = xkeys[a];
+        for (int ax = 0; ax < D; ++ax)
+            for (int bit = 0; bit < s0; ++bit) iA[ax] |= (int64_t)((key >> (bit * D + ax)) & 1) << bit;
+    }
+    int lead[2] = {0, 0};
+    {
+        int r = line;
+        for (int ax = D - 2; ax >= 0; --ax) {
+            lead[ax] = r % P;
+            r /= P;
+        }
+    }
+    const int E = s0 + L;
+    const double inv_den = 1.0 / ldexp((double)Q, E);
+    const double inv_qs = 1.0 / ldexp((double)Q, s0);
+    const int2 lr = box_leaf[b];
+    const int t0 = leaf_beg[lr.x], t1 = leaf_beg[lr.y];
+    double2 acc[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) acc[l] = make_double2(0.0, 0.0);
+    for (int t = t0; t < t1; ++t) {
+        double2 w = f[perm[t]];
+#pragma unroll
+        for (int ax = 0; ax < D - 1; ++ax)
+            w = cmul(w, expi_turns(direct_turns<Q>(Q * iA[ax] + lead[ax], sm[(int64_t)t * D + ax],
+                                                   sloc[(int64_t)t * D + ax], E, inv_den, inv_qs, N)));
+        const int m = sm[(int64_t)t * D + D - 1];
+        const double loc = sloc[(int64_t)t * D + D - 1];
+        double2 e = expi_turns(direct_turns<Q>(Q * iA[D - 1], m, loc, E, inv_den, inv_qs, N));
+        const double2 r = sratio[t];
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            const double2 we = cmul(w, e);
+            acc[l].x += we.x;
+            acc[l].y += we.y;
+            e = cmul(e, r);
+        }
+    }
+    typename CV<S>::t *o = state + ab * PD + (int64_t)line * P;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        typename CV<S>::t v;
+        v.x = (S)acc[l].x;
+        v.y = (S)acc[l].y;
+        o[l] = v;
+    }
+}
+
 // index of the descriptor owning flat item `i` (prefix[t] <= i < prefix[t+1])
 __device__ __forceinline__ int owner(const int64_t *__restrict__ prefix, int n, int64_t i)
 {
@@ -385,6 +515,64 @@ void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t
         tb.mf = (double *)arena.alloc(sizeof(double) * translate_mfma_table_doubles(p));
         build_mfma_tables(tb, p, tb.mf, s);
     }
+}
+
+void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rho, Arena &arena, hipStream_t s)
+{
+    st.s0 = s0;
+    if (s0 == 0 || tk.npts == 0) return;
+    const int L = tk.L, l0 = L - s0;
+    // leaves under every box of T_K level l0, composed from the child ranges
+    std::vector<int2> br((size_t)tk.count[l0]);
+    for (int64_t b = 0; b < tk.count[l0]; ++b) {
+        int32_t lo = (int32_t)b, hi = (int32_t)b + 1;
+        for (int m = l0; m < L; ++m) {
+            lo = tk.child_beg_host[m][lo];
+            hi = tk.child_beg_host[m][hi];
+        }
+        br[(size_t)b] = make_int2(lo, hi);
+    }
+    st.box_leaf = (int2 *)arena.alloc(sizeof(int2) * br.size());
+    BF_HIP(hipMemcpyAsync(st.box_leaf, br.data(), sizeof(int2) * br.size(), hipMemcpyHostToDevice, s));
+    st.sm = (int32_t *)arena.alloc(sizeof(int32_t) * (size_t)tk.npts * d);
+    st.sloc = (double *)arena.alloc(sizeof(double) * (size_t)tk.npts * d);
+    st.sratio = (double2 *)arena.alloc(sizeof(double2) * (size_t)tk.npts);
+    if (d == 2)
+        k_source_offsets<2><<<nblk(tk.npts, 256), 256, 0, s>>>(tk.npts, s0, q, rho, tk.perm, tk.leaf_of,
+                                                               tk.keys[L], tk.local, st.sm, st.sloc, st.sratio);
+    else
+        k_source_offsets<3><<<nblk(tk.npts, 256), 256, 0, s>>>(tk.npts, s0, q, rho, tk.perm, tk.leaf_of,
+                                                               tk.keys[L], tk.local, st.sm, st.sloc, st.sratio);
+    BF_HIP(hipGetLastError());
+    BF_HIP(hipStreamSynchronize(s));  // br is a host temporary
+}
+
+void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
+                   int64_t N, void *state)
+{
+    const int L = tk.L, s0 = st.s0, l0 = L - s0;
+    const int64_t nA = tx.count[s0], nB = tk.count[l0];
+    int PL = c.d == 2 ? c.p : c.p * c.p;
+    const int64_t n = nA * nB * PL;
+    if (n == 0) return;
+    const bool f32 = c.precision != BFSFT_FP64;
+    auto go = [&](auto dd, auto tag) {
+        constexpr int D = decltype(dd)::value;
+        constexpr int P = decltype(tag)::value;
+        if (f32)
+            k_direct<D, P, float><<<nblk(n, 256), 256, 0, c.stream>>>(
+                s0, L, N, nA, nB, tx.keys[s0], st.box_leaf, tk.leaf_beg, tk.perm, st.sm, st.sloc, st.sratio,
+                (const double2 *)f, (float2 *)state);
+        else
+            k_direct<D, P, double><<<nblk(n, 256), 256, 0, c.stream>>>(
+                s0, L, N, nA, nB, tx.keys[s0], st.box_leaf, tk.leaf_beg, tk.perm, st.sm, st.sloc, st.sratio,
+                (const double2 *)f, (double2 *)state);
+    };
+    if (c.d == 2)
+        dispatch_p(c.p, [&](auto tag) { go(std::integral_constant<int, 2>{}, tag); });
+    else
+        dispatch_p3(c.p, [&](auto tag) { go(std::integral_constant<int, 3>{}, tag); });
+    BF_HIP(hipGetLastError());
 }
 
 void launch_leaf(const Launch &c, const double *f, const Tree &tk, double, void *state)

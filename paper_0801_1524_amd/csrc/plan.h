@@ -17,6 +17,7 @@ struct bfsft_plan {
     // ---- one transform
     bfsft::Tree tx, tk;
     bfsft::Tables tb;
+    bfsft::StartLevel start;            // the sweep begins at T_K level L - start.s0
     int lds = 0;                        // LDS budget of a translation tile (bytes), most levels
     std::vector<int> lds_level;         // per T_K level l: tile LDS budget (bytes)
     std::vector<int> kind;              // per T_K level l: 0 VALU kernel, 1 matrix-core kernel
@@ -73,6 +74,7 @@ void build_plan(bfsft_plan *P, const double *x, const double *k);
 void release_plan(bfsft_plan *P);
 int ceil_log2(int64_t N);
 int64_t env_cap();
+int choose_start(const bfsft_plan *P);
 
 // autotuning cache (text file, one "key value..." line per entry)
 bool tune_lookup(const std::string &key, std::vector<int> &vals);

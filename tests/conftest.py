@@ -14,6 +14,13 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: larger CPU oracle runs")
 
 
+@pytest.fixture(autouse=True)
+def leaf_start(monkeypatch):
+    """Plans start the sweep at the leaves (Section 2.2, step 2) unless a test
+    asks for another start level; the start-level tests set it themselves."""
+    monkeypatch.setenv("BFSFT_START_LEVEL", "0")
+
+
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
