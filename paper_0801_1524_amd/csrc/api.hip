@@ -375,7 +375,7 @@ void build_tiles(bfsft_plan *P, int lds_bytes)
 // which potentials are summed directly), chosen from the tree counts alone so
 // that it never depends on timing: the s0 that minimises a cost model (ns on
 // one MI355X, constants fitted to the kernels' measured times)
-//   direct sums at level L - s0:  0.010 (1 + 0.15 (d - 2)) per pair, source and
+//   direct sums at level L - s0:  0.0066 (1 + 0.15 (d - 2)) per pair, source and
 //                                 line of p^(d-1),
 //   translations below it:        (d = 2: 6.4e-4, d = 3: 1.54e-3) p^(d+1) per pair,
 //   leaf initialisation (s0 = 0): 5.7e-3 per source and grid point.
@@ -394,7 +394,7 @@ int choose_start(const bfsft_plan *P)
     const double lines = d == 2 ? p : p * p;
     auto pairs = [&](int l) { return (double)P->tx.count[L - l] * (double)P->tk.count[l]; };
     const double tr = (d == 2 ? 6.4e-4 : 1.54e-3) * std::pow(p, d + 1);
-    const double dr = 0.010 * (1.0 + 0.15 * (d - 2));
+    const double dr = 0.0066 * (1.0 + 0.15 * (d - 2));
     std::vector<double> below(L + 1, 0.0);  // below[l0]: translations producing levels < l0
     for (int l = 1; l <= L; ++l) below[l] = below[l - 1] + tr * pairs(l - 1);
     const double leaf_cost = 5.7e-3 * (double)P->nk * std::pow(p, d) + below[L];

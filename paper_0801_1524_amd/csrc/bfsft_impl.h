@@ -153,7 +153,7 @@ struct StartLevel {
     int2 *box_leaf = nullptr;   // [count_K[L - s0]] leaf range of every box of T_K level L - s0
     int32_t *sm = nullptr;      // [npts][d] leaf index mod 2^s0 of every source (sorted order)
     double *sloc = nullptr;     // [npts][d] offset inside its leaf (sorted order)
-    double2 *sratio = nullptr;  // [npts] phase step of the last axis between grid points
+    double2 *sratio = nullptr;  // [npts][d] phase step between grid points, per axis
 };
 // s0 <= 18 keeps the exact phase reduction of the direct sums in 64-bit integers
 constexpr int kStartMax = 18;

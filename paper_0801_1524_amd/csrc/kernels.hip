@@ -207,7 +207,8 @@ __global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
 // 2^s0 (an integer), loc = offset inside the leaf (exact).
 
 // offsets of the sources, in the trees' sorted order
-// and the phase step of the last axis, exp(2 pi i (rho m + loc) / (q 2^s0))
+// and the phase step between grid points of every axis,
+// exp(2 pi i (rho m + loc) / (q 2^s0))
 template <int D>
 __global__ void k_source_offsets(int64_t n, int s0, int q, double rho, const int32_t *__restrict__ perm,
                                  const int32_t *__restrict__ leaf_of, const uint64_t *__restrict__ leaf_keys,
@@ -224,11 +225,9 @@ __global__ void k_source_offsets(int64_t n, int s0, int q, double rho, const int
         for (int b = 0; b < s0; ++b) m |= (int)((key >> (b * D + a)) & 1) << b;
         sm[t * D + a] = m;
         sloc[t * D + a] = local[(int64_t)j * D + a];
-        if (a == D - 1) {
-            double sn, cs;
-            sincospi(2.0 * (rho * m + local[(int64_t)j * D + a]) / ldexp((double)q, s0), &sn, &cs);
-            sratio[t] = make_double2(cs, sn);
-        }
+        double sn, cs;
+        sincospi(2.0 * (rho * m + local[(int64_t)j * D + a]) / ldexp((double)q, s0), &sn, &cs);
+        sratio[t * D + a] = make_double2(cs, sn);
     }
 }
 
@@ -253,9 +252,13 @@ __device__ __forceinline__ double2 expi_turns(double t)
     return make_double2(c, s);
 }
 
-// one thread per (pair, line): a line fixes the grid indices of the leading
-// d - 1 axes; the p values along the last axis use a phase recurrence
-template <int D, int P, typename S>
+// One thread per (pair, group of G lines).  A line fixes the grid indices
+// of the leading d - 1 axes; a group holds G consecutive indices of axis
+// d - 2.  Per source the thread takes one phase per leading axis and one
+// along the last axis from sincospi, steps along axis d - 2 (G values) and
+// along the last axis (p values) by the source's per-axis phase steps, and
+// accumulates G x p outputs.
+template <int D, int P, int G, typename S>
 __global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_t nA, int64_t nB,
                                                const uint64_t *__restrict__ xkeys,
                                                const int2 *__restrict__ box_leaf,
@@ -263,17 +266,18 @@ __global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_
                                                const int32_t *__restrict__ perm,
                                                const int32_t *__restrict__ sm,
                                                const double *__restrict__ sloc,
-                                               const double2 *__restrict__ sratio,
+                                               const double2 *__restrict__ sstep,
                                                const double2 *__restrict__ f,
                                                typename CV<S>::t *__restrict__ state)
 {
     constexpr int Q = P - 1;
-    constexpr int PL = D == 2 ? P : P * P;  // lines per pair
-    constexpr int PD = PL * P;
+    constexpr int NG = (P + G - 1) / G;              // groups along axis d - 2
+    constexpr int GL = D == 2 ? NG : P * NG;         // groups per pair
+    constexpr int PD = D == 2 ? P * P : P * P * P;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= nA * nB * PL) return;
-    const int64_t ab = gid / PL;
-    const int line = (int)(gid - ab * PL);
+    if (gid >= nA * nB * GL) return;
+    const int64_t ab = gid / GL;
+    const int grp = (int)(gid - ab * GL);
     const int64_t a = ab / nB, b = ab - a * nB;
     int64_t iA[3] = {0, 0, 0};
     {
@@ -281,47 +285,56 @@ __global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_
         for (int ax = 0; ax < D; ++ax)
             for (int bit = 0; bit < s0; ++bit) iA[ax] |= (int64_t)((key >> (bit * D + ax)) & 1) << bit;
     }
-    int lead[2] = {0, 0};
-    {
-        int r = line;
-        for (int ax = D - 2; ax >= 0; --ax) {
-            lead[ax] = r % P;
-            r /= P;
-        }
-    }
+    // grid index of axis 0 (3D only) and the first index of the group on axis d - 2
+    const int l_outer = D == 3 ? grp / NG : 0;
+    const int lg0 = (D == 3 ? grp - l_outer * NG : grp) * G;
     const int E = s0 + L;
     const double inv_den = 1.0 / ldexp((double)Q, E);
     const double inv_qs = 1.0 / ldexp((double)Q, s0);
     const int2 lr = box_leaf[b];
     const int t0 = leaf_beg[lr.x], t1 = leaf_beg[lr.y];
-    double2 acc[P];
+    double2 acc[G][P];
 #pragma unroll
-    for (int l = 0; l < P; ++l) acc[l] = make_double2(0.0, 0.0);
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int l = 0; l < P; ++l) acc[g][l] = make_double2(0.0, 0.0);
     for (int t = t0; t < t1; ++t) {
         double2 w = f[perm[t]];
+        if (D == 3)
+            w = cmul(w, expi_turns(direct_turns<Q>(Q * iA[0] + l_outer, sm[(int64_t)t * D], sloc[(int64_t)t * D],
+                                                   E, inv_den, inv_qs, N)));
+        constexpr int AG = D - 2, AL = D - 1;  // the group axis and the last axis
+        double2 c[G];
+        c[0] = cmul(w, expi_turns(direct_turns<Q>(Q * iA[AG] + lg0, sm[(int64_t)t * D + AG],
+                                                  sloc[(int64_t)t * D + AG], E, inv_den, inv_qs, N)));
+        const double2 rg = sstep[(int64_t)t * D + AG];
 #pragma unroll
-        for (int ax = 0; ax < D - 1; ++ax)
-            w = cmul(w, expi_turns(direct_turns<Q>(Q * iA[ax] + lead[ax], sm[(int64_t)t * D + ax],
-                                                   sloc[(int64_t)t * D + ax], E, inv_den, inv_qs, N)));
-        const int m = sm[(int64_t)t * D + D - 1];
-        const double loc = sloc[(int64_t)t * D + D - 1];
-        double2 e = expi_turns(direct_turns<Q>(Q * iA[D - 1], m, loc, E, inv_den, inv_qs, N));
-        const double2 r = sratio[t];
+        for (int g = 1; g < G; ++g) c[g] = cmul(c[g - 1], rg);
+        double2 e = expi_turns(direct_turns<Q>(Q * iA[AL], sm[(int64_t)t * D + AL], sloc[(int64_t)t * D + AL], E,
+                                               inv_den, inv_qs, N));
+        const double2 rl = sstep[(int64_t)t * D + AL];
 #pragma unroll
         for (int l = 0; l < P; ++l) {
-            const double2 we = cmul(w, e);
-            acc[l].x += we.x;
-            acc[l].y += we.y;
-            e = cmul(e, r);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double2 v = cmul(c[g], e);
+                acc[g][l].x += v.x;
+                acc[g][l].y += v.y;
+            }
+            e = cmul(e, rl);
         }
     }
-    typename CV<S>::t *o = state + ab * PD + (int64_t)line * P;
+    typename CV<S>::t *o = state + ab * PD + ((int64_t)l_outer * P + lg0) * P;
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
-        typename CV<S>::t v;
-        v.x = (S)acc[l].x;
-        v.y = (S)acc[l].y;
-        o[l] = v;
+    for (int g = 0; g < G; ++g) {
+        if (lg0 + g >= P) break;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            typename CV<S>::t v;
+            v.x = (S)acc[g][l].x;
+            v.y = (S)acc[g][l].y;
+            o[g * P + l] = v;
+        }
     }
 }
 
@@ -536,7 +549,7 @@ void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rh
     BF_HIP(hipMemcpyAsync(st.box_leaf, br.data(), sizeof(int2) * br.size(), hipMemcpyHostToDevice, s));
     st.sm = (int32_t *)arena.alloc(sizeof(int32_t) * (size_t)tk.npts * d);
     st.sloc = (double *)arena.alloc(sizeof(double) * (size_t)tk.npts * d);
-    st.sratio = (double2 *)arena.alloc(sizeof(double2) * (size_t)tk.npts);
+    st.sratio = (double2 *)arena.alloc(sizeof(double2) * (size_t)tk.npts * d);
     if (d == 2)
         k_source_offsets<2><<<nblk(tk.npts, 256), 256, 0, s>>>(tk.npts, s0, q, rho, tk.perm, tk.leaf_of,
                                                                tk.keys[L], tk.local, st.sm, st.sloc, st.sratio);
@@ -552,19 +565,20 @@ void launch_direct(const Launch &c, const StartLevel &st, const double *f, const
 {
     const int L = tk.L, s0 = st.s0, l0 = L - s0;
     const int64_t nA = tx.count[s0], nB = tk.count[l0];
-    int PL = c.d == 2 ? c.p : c.p * c.p;
-    const int64_t n = nA * nB * PL;
-    if (n == 0) return;
+    if (nA * nB == 0) return;
     const bool f32 = c.precision != BFSFT_FP64;
     auto go = [&](auto dd, auto tag) {
         constexpr int D = decltype(dd)::value;
         constexpr int P = decltype(tag)::value;
+        constexpr int G = 3;
+        constexpr int NG = (P + G - 1) / G;
+        const int64_t n = nA * nB * (D == 2 ? NG : P * NG);
         if (f32)
-            k_direct<D, P, float><<<nblk(n, 256), 256, 0, c.stream>>>(
+            k_direct<D, P, G, float><<<nblk(n, 256), 256, 0, c.stream>>>(
                 s0, L, N, nA, nB, tx.keys[s0], st.box_leaf, tk.leaf_beg, tk.perm, st.sm, st.sloc, st.sratio,
                 (const double2 *)f, (float2 *)state);
         else
-            k_direct<D, P, double><<<nblk(n, 256), 256, 0, c.stream>>>(
+            k_direct<D, P, G, double><<<nblk(n, 256), 256, 0, c.stream>>>(
                 s0, L, N, nA, nB, tx.keys[s0], st.box_leaf, tk.leaf_beg, tk.perm, st.sm, st.sloc, st.sratio,
                 (const double2 *)f, (double2 *)state);
     };
