@@ -383,7 +383,7 @@ void build_tiles(bfsft_plan *P, int lds_bytes)
 // modelled time.  BFSFT_START_LEVEL=n forces n (clamped to [0, min(L, kStartMax)]).
 int choose_start(const bfsft_plan *P)
 {
-    if (P->nx == 0 || P->nk == 0 || P->valu_only) return 0;
+    if (P->nx == 0 || P->nk == 0) return 0;
     const int L = P->L, d = P->d;
     if (const char *e = std::getenv("BFSFT_START_LEVEL")) {
         char *end = nullptr;

@@ -55,7 +55,8 @@ void build_steps(bfsft_plan *B)
         std::vector<unsigned char> descs;
         std::vector<int64_t> prefix;
         for (bfsft_plan *S : B->subs) {
-            if (!active(S) || S->L < s) continue;
+            // transform S translates at steps start + 1 .. L
+            if (!active(S) || S->L < s || s <= S->start.s0) continue;
             const int l = S->L - s;
             const LevelArgs la = level_args(S, l, S->buf[(s - 1) & 1], S->buf[s & 1]);
             const int64_t items = translate_items(la);
@@ -77,12 +78,22 @@ void build_steps(bfsft_plan *B)
 void build_leaf_final(bfsft_plan *B)
 {
     std::vector<LeafDesc> ld;
+    std::vector<DirectDesc> dd;
     std::vector<FinalDesc> fd;
-    std::vector<int64_t> lp, fp;
-    int64_t lt = 0, ft = 0;
+    std::vector<int64_t> lp, dp, fp;
+    int64_t lt = 0, dt = 0, ft = 0;
     for (size_t t = 0; t < B->subs.size(); ++t) {
         bfsft_plan *S = B->subs[t];
         if (!active(S)) continue;
+        if (S->start.s0 > 0) {
+            // the state of level L - s0 goes where step s0 + 1 reads it
+            DirectDesc a = direct_desc(S->start, B->f_stage + 2 * B->f_off[t], S->tx, S->tk, S->N,
+                                       S->buf[S->start.s0 & 1]);
+            a.first = dt;
+            dp.push_back(dt);
+            dt += direct_items(S->d, S->p, a);
+            dd.push_back(a);
+        }
         LeafDesc a;
         a.f = B->f_stage + 2 * B->f_off[t];
         a.perm = S->tk.perm;
@@ -91,9 +102,11 @@ void build_leaf_final(bfsft_plan *B)
         a.state = S->buf[0];
         a.nleaf = S->tk.count[S->L];
         a.first = lt;
-        lp.push_back(lt);
-        lt += a.nleaf * S->PD;
-        ld.push_back(a);
+        if (S->start.s0 == 0) {
+            lp.push_back(lt);
+            lt += a.nleaf * S->PD;
+            ld.push_back(a);
+        }
         FinalDesc b;
         b.state = S->buf[S->L & 1];
         b.leaf_of = S->tx.leaf_of;
@@ -111,6 +124,10 @@ void build_leaf_final(bfsft_plan *B)
     B->leaf_prefix = upload(B, lp);
     B->leaf_n = (int)ld.size();
     B->leaf_total = lt;
+    B->direct_desc = upload(B, dd);
+    B->direct_prefix = upload(B, dp);
+    B->direct_n = (int)dd.size();
+    B->direct_total = dt;
     B->final_desc = upload(B, fd);
     B->final_prefix = upload(B, fp);
     B->final_n = (int)fd.size();
@@ -123,6 +140,7 @@ void enqueue(bfsft_plan *B, hipStream_t s)
     // item counters of all steps start at zero (a kernel, not a memset node)
     launch_zero_u64(B->step_next, (int64_t)B->steps.size(), s);
     launch_leaf_batched(c, B->leaf_desc, B->leaf_prefix, B->leaf_n, B->leaf_total);
+    launch_direct_batched(c, B->direct_desc, B->direct_prefix, B->direct_n, B->direct_total);
     for (size_t i = 0; i < B->steps.size(); ++i) {
         const bfsft_plan::Step &st = B->steps[i];
         launch_translate_batched(c, st.desc, st.prefix, st.ndesc, st.total, st.lds, B->grid, B->step_next + i);

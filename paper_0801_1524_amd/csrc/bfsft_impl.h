@@ -161,6 +161,26 @@ void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rh
 void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
                    int64_t N, void *state);
 
+// one transform of a (batched) direct start-level launch
+struct DirectDesc {
+    int s0, L;
+    int64_t N, nA, nB;          // pairs: T_X boxes of level s0 x T_K boxes of level L - s0
+    const uint64_t *xkeys;      // T_X keys of level s0
+    const int2 *box_leaf;
+    const int32_t *leaf_beg;
+    const int32_t *perm;
+    const int32_t *sm;
+    const double *sloc;
+    const double2 *sstep;
+    const double2 *f;           // sources, original order
+    void *state;                // output state of level L - s0
+    int64_t first;              // first flat item (batched)
+};
+DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, const Tree &tk, int64_t N,
+                       void *state);
+int64_t direct_items(int d, int p, const DirectDesc &dd);
+void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t *prefix, int n, int64_t total);
+
 // matrix-core (MFMA) 2D translation with FP64 arithmetic (mixed and FP64)
 bool translate_mfma_supported(int d, int p, int precision);
 size_t translate_mfma_table_doubles(int p);

@@ -258,30 +258,24 @@ __device__ __forceinline__ double2 expi_turns(double t)
 // along the last axis from sincospi, steps along axis d - 2 (G values) and
 // along the last axis (p values) by the source's per-axis phase steps, and
 // accumulates G x p outputs.
+template <int D, int P, int G> constexpr int direct_groups() { return D == 2 ? (P + G - 1) / G : P * ((P + G - 1) / G); }
+
 template <int D, int P, int G, typename S>
-__global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_t nA, int64_t nB,
-                                               const uint64_t *__restrict__ xkeys,
-                                               const int2 *__restrict__ box_leaf,
-                                               const int32_t *__restrict__ leaf_beg,
-                                               const int32_t *__restrict__ perm,
-                                               const int32_t *__restrict__ sm,
-                                               const double *__restrict__ sloc,
-                                               const double2 *__restrict__ sstep,
-                                               const double2 *__restrict__ f,
-                                               typename CV<S>::t *__restrict__ state)
+__device__ __forceinline__ void direct_item(const DirectDesc &dd, int64_t gid)
 {
     constexpr int Q = P - 1;
     constexpr int NG = (P + G - 1) / G;              // groups along axis d - 2
-    constexpr int GL = D == 2 ? NG : P * NG;         // groups per pair
+    constexpr int GL = direct_groups<D, P, G>();     // groups per pair
     constexpr int PD = D == 2 ? P * P : P * P * P;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= nA * nB * GL) return;
+    const int s0 = dd.s0, L = dd.L;
+    const int64_t N = dd.N, nB = dd.nB;
+    if (gid >= dd.nA * nB * GL) return;
     const int64_t ab = gid / GL;
     const int grp = (int)(gid - ab * GL);
     const int64_t a = ab / nB, b = ab - a * nB;
     int64_t iA[3] = {0, 0, 0};
     {
-        const uint64_t key = xkeys[a];
+        const uint64_t key = dd.xkeys[a];
         for (int ax = 0; ax < D; ++ax)
             for (int bit = 0; bit < s0; ++bit) iA[ax] |= (int64_t)((key >> (bit * D + ax)) & 1) << bit;
     }
@@ -291,15 +285,18 @@ __global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_
     const int E = s0 + L;
     const double inv_den = 1.0 / ldexp((double)Q, E);
     const double inv_qs = 1.0 / ldexp((double)Q, s0);
-    const int2 lr = box_leaf[b];
-    const int t0 = leaf_beg[lr.x], t1 = leaf_beg[lr.y];
+    const int2 lr = dd.box_leaf[b];
+    const int t0 = dd.leaf_beg[lr.x], t1 = dd.leaf_beg[lr.y];
+    const int32_t *__restrict__ sm = dd.sm;
+    const double *__restrict__ sloc = dd.sloc;
+    const double2 *__restrict__ sstep = dd.sstep;
     double2 acc[G][P];
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int l = 0; l < P; ++l) acc[g][l] = make_double2(0.0, 0.0);
     for (int t = t0; t < t1; ++t) {
-        double2 w = f[perm[t]];
+        double2 w = dd.f[dd.perm[t]];
         if (D == 3)
             w = cmul(w, expi_turns(direct_turns<Q>(Q * iA[0] + l_outer, sm[(int64_t)t * D], sloc[(int64_t)t * D],
                                                    E, inv_den, inv_qs, N)));
@@ -324,7 +321,7 @@ __global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_
             e = cmul(e, rl);
         }
     }
-    typename CV<S>::t *o = state + ab * PD + ((int64_t)l_outer * P + lg0) * P;
+    typename CV<S>::t *o = (typename CV<S>::t *)dd.state + ab * PD + ((int64_t)l_outer * P + lg0) * P;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (lg0 + g >= P) break;
@@ -336,6 +333,12 @@ __global__ __launch_bounds__(256) void k_direct(int s0, int L, int64_t N, int64_
             o[g * P + l] = v;
         }
     }
+}
+
+template <int D, int P, int G, typename S>
+__global__ __launch_bounds__(256) void k_direct(DirectDesc dd)
+{
+    direct_item<D, P, G, S>(dd, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // index of the descriptor owning flat item `i` (prefix[t] <= i < prefix[t+1])
@@ -359,6 +362,17 @@ __global__ __launch_bounds__(256) void k_leaf_batched(int p, const LeafDesc *__r
     const LeafDesc &d = ds[owner(prefix, n, i)];
     leaf_item<D, S>(p, d.nleaf, (const double2 *)d.f, d.perm, d.beg, d.local,
                     (typename CV<S>::t *)d.state, i - d.first);
+}
+
+template <int D, int P, int G, typename S>
+__global__ __launch_bounds__(256) void k_direct_batched(const DirectDesc *__restrict__ ds,
+                                                       const int64_t *__restrict__ prefix, int n,
+                                                       int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const DirectDesc &d = ds[owner(prefix, n, i)];
+    direct_item<D, P, G, S>(d, i - d.first);
 }
 
 // ----------------------------------------------------------------- final --
@@ -560,27 +574,70 @@ void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rh
     BF_HIP(hipStreamSynchronize(s));  // br is a host temporary
 }
 
+constexpr int kDirectG = 3;  // grid lines per thread of the direct sums
+
+DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, const Tree &tk, int64_t N,
+                       void *state)
+{
+    DirectDesc d;
+    d.s0 = st.s0;
+    d.L = tk.L;
+    d.N = N;
+    d.nA = tx.count[st.s0];
+    d.nB = tk.count[tk.L - st.s0];
+    d.xkeys = tx.keys[st.s0];
+    d.box_leaf = st.box_leaf;
+    d.leaf_beg = tk.leaf_beg;
+    d.perm = tk.perm;
+    d.sm = st.sm;
+    d.sloc = st.sloc;
+    d.sstep = st.sratio;
+    d.f = (const double2 *)f;
+    d.state = state;
+    d.first = 0;
+    return d;
+}
+
+int64_t direct_items(int d, int p, const DirectDesc &dd)
+{
+    const int ng = (p + kDirectG - 1) / kDirectG;
+    return dd.nA * dd.nB * (d == 2 ? ng : p * ng);
+}
+
 void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
                    int64_t N, void *state)
 {
-    const int L = tk.L, s0 = st.s0, l0 = L - s0;
-    const int64_t nA = tx.count[s0], nB = tk.count[l0];
-    if (nA * nB == 0) return;
+    const DirectDesc dd = direct_desc(st, f, tx, tk, N, state);
+    const int64_t n = direct_items(c.d, c.p, dd);
+    if (n == 0) return;
     const bool f32 = c.precision != BFSFT_FP64;
-    auto go = [&](auto dd, auto tag) {
-        constexpr int D = decltype(dd)::value;
+    auto go = [&](auto dim, auto tag) {
+        constexpr int D = decltype(dim)::value;
         constexpr int P = decltype(tag)::value;
-        constexpr int G = 3;
-        constexpr int NG = (P + G - 1) / G;
-        const int64_t n = nA * nB * (D == 2 ? NG : P * NG);
         if (f32)
-            k_direct<D, P, G, float><<<nblk(n, 256), 256, 0, c.stream>>>(
-                s0, L, N, nA, nB, tx.keys[s0], st.box_leaf, tk.leaf_beg, tk.perm, st.sm, st.sloc, st.sratio,
-                (const double2 *)f, (float2 *)state);
+            k_direct<D, P, kDirectG, float><<<nblk(n, 256), 256, 0, c.stream>>>(dd);
         else
-            k_direct<D, P, G, double><<<nblk(n, 256), 256, 0, c.stream>>>(
-                s0, L, N, nA, nB, tx.keys[s0], st.box_leaf, tk.leaf_beg, tk.perm, st.sm, st.sloc, st.sratio,
-                (const double2 *)f, (double2 *)state);
+            k_direct<D, P, kDirectG, double><<<nblk(n, 256), 256, 0, c.stream>>>(dd);
+    };
+    if (c.d == 2)
+        dispatch_p(c.p, [&](auto tag) { go(std::integral_constant<int, 2>{}, tag); });
+    else
+        dispatch_p3(c.p, [&](auto tag) { go(std::integral_constant<int, 3>{}, tag); });
+    BF_HIP(hipGetLastError());
+}
+
+void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t *prefix, int n, int64_t total)
+{
+    if (total == 0) return;
+    const bool f32 = c.precision != BFSFT_FP64;
+    const int g = nblk(total, 256);
+    auto go = [&](auto dim, auto tag) {
+        constexpr int D = decltype(dim)::value;
+        constexpr int P = decltype(tag)::value;
+        if (f32)
+            k_direct_batched<D, P, kDirectG, float><<<g, 256, 0, c.stream>>>(ds, prefix, n, total);
+        else
+            k_direct_batched<D, P, kDirectG, double><<<g, 256, 0, c.stream>>>(ds, prefix, n, total);
     };
     if (c.d == 2)
         dispatch_p(c.p, [&](auto tag) { go(std::integral_constant<int, 2>{}, tag); });

@@ -51,6 +51,10 @@ struct bfsft_plan {
     int64_t *leaf_prefix = nullptr;
     int leaf_n = 0;
     int64_t leaf_total = 0;
+    bfsft::DirectDesc *direct_desc = nullptr;  // transforms that start above their leaves
+    int64_t *direct_prefix = nullptr;
+    int direct_n = 0;
+    int64_t direct_total = 0;
     bfsft::FinalDesc *final_desc = nullptr;
     int64_t *final_prefix = nullptr;
     int final_n = 0;

@@ -132,3 +132,52 @@ def test_adjoint_auto_start_vs_direct(bf, oracle_mod, monkeypatch):
     S = np.arange(0, P.nk, 7)
     vd = np.conj(oracle_mod.direct(P.k, P.x, np.conj(g), P.N, S))
     assert rel_l2(v[S], vd) <= EPS[P.p]
+
+
+# ------------------------------------------------------------------ batched
+
+def _batch(count=7, seed=11):
+    return synth.batched_config(count=count, p=7, nmin=48, nmax=1500, seed=seed)
+
+
+def _split(u, probs):
+    out, o = [], 0
+    for q in probs:
+        out.append(u[o:o + q.nx])
+        o += q.nx
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_forced_start_vs_serial_and_oracle(bf, oracle_mod, monkeypatch, precision):
+    """Every transform starts 2 levels above its leaves: the batched graph
+    (a direct-sum launch for all transforms, then the steps) equals the same
+    transforms run one by one, and each equals the oracle with start 2."""
+    monkeypatch.setenv("BFSFT_START_LEVEL", "2")
+    probs = _batch()
+    B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, precision)
+    f = np.concatenate([q.f for q in probs])
+    ug = B.execute(f).cpu().numpy()
+    us = B.execute(f, serial=True).cpu().numpy()
+    B.close()
+    assert rel_l2(ug, us) <= 1e-14
+    tol = {"fp64": 1e-10, "mixed": 2e-6}[precision]
+    for q, u in zip(probs, _split(ug, probs)):
+        ub = oracle_mod.Butterfly(2, q.N, q.p, q.x, q.k).run(q.f, start_level=2)
+        assert rel_l2(u, ub) <= tol, (q.name, q.N)
+
+
+def test_batched_auto_start_vs_serial_and_direct(bf, oracle_mod, monkeypatch):
+    """Each transform with its own chosen start level (the 1-per-unit-length
+    curves start above the leaves): graph equals serial, outputs within the
+    method's accuracy of the direct sum."""
+    monkeypatch.delenv("BFSFT_START_LEVEL", raising=False)
+    probs = _batch(count=9, seed=4)
+    B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, "fp64")
+    f = np.concatenate([q.f for q in probs])
+    ug = B.execute(f).cpu().numpy()
+    us = B.execute(f, serial=True).cpu().numpy()
+    B.close()
+    assert rel_l2(ug, us) <= 1e-14
+    for q, u in zip(probs, _split(ug, probs)):
+        assert rel_l2(u, oracle_mod.direct(q.x, q.k, q.f, q.N)) <= EPS[7], (q.name, q.N)
