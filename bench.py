@@ -218,10 +218,10 @@ def time_precision(bf, torch, P, precision, steps, warmup):
 
 def roofline(res, precision):
     info, tm = res["info"], res["timing"]
-    L = info["levels"]
-    launches = L * tm["executes"]
+    nlev = info["levels"] - info["start_level"]                   # translation launches per execute
+    launches = nlev * tm["executes"]
     t_avg = sum(tm["translate_ms"]) / launches / 1e3           # s per launch
-    bytes_avg = info["sweep_bytes"] / L                           # algorithmic bytes per launch
+    bytes_avg = info["sweep_bytes"] / nlev                        # algorithmic bytes per launch
     achieved = bytes_avg / t_avg / 1e9
     traffic = traffic_from_profile(precision)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -229,8 +229,8 @@ def roofline(res, precision):
             "traffic": traffic,
             "kernel": "k_translate2d" if info["d"] == 2 else "k_translate3d", "avg_launch_ms": round(t_avg * 1e3, 4),
             "alg_bytes_per_launch": bytes_avg,
-            "alg_flops_per_launch": info["sweep_flops"] / L,
-            "alg_tflops": round(info["sweep_flops"] / L / t_avg / 1e12, 2)}
+            "alg_flops_per_launch": info["sweep_flops"] / nlev,
+            "alg_tflops": round(info["sweep_flops"] / nlev / t_avg / 1e12, 2)}
 
 
 def cpu_baseline_leg(P, gpu_results, S):
@@ -331,7 +331,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "nx": P.nx, "nk": P.nk, "levels": r["info"]["levels"], "precision": head,
-                   "state_dtype": "f64" if head == "fp64" else "f32"},
+                   "state_dtype": "f64" if head == "fp64" else "f32",
+                   "start_level": r["info"]["start_level"]},
         "err_rel_l2": errs[head],
         "gate_passed": errs[head] is not None and errs[head] <= GATE,
         "roofline": roofline(r, head),
@@ -339,6 +340,8 @@ def main():
         "precisions": {k: {"outputs_per_s": round(P.nx / (v["ms_per_step"] / 1e3), 1),
                            "ms_per_step": round(v["ms_per_step"], 4),
                            "translate_ms_per_step": round(sum(v["timing"]["translate_ms"]) / v["timing"]["executes"], 4),
+                           # leaf initialisation, or the direct sums of a start above the leaves
+                           "start_ms_per_step": round(v["timing"]["leaf_ms"] / v["timing"]["executes"], 4),
                            "err_rel_l2": errs[k],
                            "roofline_frac": roofline(v, k)["frac"]}
                        for k, v in results.items()},

@@ -63,7 +63,8 @@ typedef struct {
                                              batched: pairs produced at sweep step s, all
                                              transforms */
     double sweep_bytes;                   /* algorithmic HBM bytes of the sweep (read + write
-                                             of every level's state, once) */
+                                             of every translated level's state, once: the
+                                             levels below levels - start_level) */
     double sweep_flops;                   /* algorithmic flops of the sweep: per output pair,
                                              2^d * d * p^(d+1) complex multiply-adds x 8 */
     int64_t device_bytes;                 /* device memory owned by the plan */

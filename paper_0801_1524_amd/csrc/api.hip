@@ -721,7 +721,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         for (int l = 0; l <= P->L; ++l) o->pairs[l] = o->x_boxes[P->L - l] * o->k_boxes[l];
         const double unit = P->d == 2 ? 48.0 * P->p * P->p * P->p : 112.0 * P->p * P->p * P->p * P->p;
         double bytes = 0, flops = 0;
-        for (int l = 0; l < P->L; ++l) {
+        for (int l = 0; l < P->L - P->start.s0; ++l) {  // the translated levels
             bytes += (double)(o->pairs[l + 1] + o->pairs[l]) * P->PD * (double)P->state_size;
             flops += (double)o->pairs[l] * unit;
         }
