@@ -115,7 +115,9 @@ def bench_batched(args, torch, bf, synth):
     print(json.dumps(line), flush=True)
 GATE = 1e-6
 COUNTERS = os.path.join(ROOT, "profiles", "translate_c2_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0801_1524_amd", "csrc", "translate.hip")
+# sources of the translation kernels (the counters are valid while these are unchanged)
+KERNEL_SRC = [os.path.join(ROOT, "paper_0801_1524_amd", "csrc", f)
+              for f in ("translate.hip", "translate_common.h", "cplx.h")]
 
 
 def log(*a):
@@ -123,7 +125,10 @@ def log(*a):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(precision):
