@@ -232,6 +232,8 @@ def roofline(res, precision):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
+            # counter bytes per launch over the same launch time (null without counters)
+            "traffic_GBps": None if traffic is None else round(traffic / t_avg / 1e9, 1),
             "kernel": "k_translate2d" if info["d"] == 2 else "k_translate3d", "avg_launch_ms": round(t_avg * 1e3, 4),
             "alg_bytes_per_launch": bytes_avg,
             "alg_flops_per_launch": info["sweep_flops"] / nlev,
