@@ -109,10 +109,11 @@ namespace {
 
 // Tiles of T_K level l: ranges [b0, b1) whose LDS cost (translate_tile_cost
 // of their children count and size) is at most `cap`, with at most 120
-// children; a single box always fits, so every tile is non-empty.
-std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap, int kind)
+// children; a single box always fits, so every tile is non-empty.  A tile
+// record is (b0, b1, cb[b0], cb[b1]): the children range comes with it.
+std::vector<int4> make_tiles(const std::vector<int32_t> &cb, int d, int cap, int kind)
 {
-    std::vector<int2> t;
+    std::vector<int4> t;
     const int n = (int)cb.size() - 1;
     if (kind == 1) cap -= 1;  // the zero block of the matrix-core kernel
     int b0 = 0;
@@ -121,7 +122,7 @@ std::vector<int2> make_tiles(const std::vector<int32_t> &cb, int d, int cap, int
         while (b1 < n && cb[b1 + 1] - cb[b0] <= 120 &&
                translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0, kind) <= cap)
             ++b1;
-        t.push_back(make_int2(b0, b1));
+        t.push_back(make_int4(b0, b1, cb[b0], cb[b1]));
         b0 = b1;
     }
     return t;
@@ -343,23 +344,23 @@ void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes, const 
     P->cost_max.assign(P->L, 0);
     P->rows.assign(P->L, 1);
     if (P->nx == 0 || P->nk == 0) return;
-    std::vector<int2> all;
+    std::vector<int4> all;
     std::vector<size_t> off(P->L);
     for (int l = 0; l < P->L; ++l) {
         const int cap = translate_cap_blocks(P->d, P->p, P->precision, lds_bytes[l]);
         const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
         const int kind = P->kind[l];
-        std::vector<int2> t = make_tiles(cb, P->d, cap, kind);
+        std::vector<int4> t = make_tiles(cb, P->d, cap, kind);
         off[l] = all.size();
         P->ntile[l] = (int)t.size();
-        for (const int2 &b : t)
+        for (const int4 &b : t)
             P->cost_max[l] =
                 std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x, kind));
         P->rows[l] = translate_rows(cap, P->cost_max[l], P->tx.count[P->L - l - 1], kind);
         all.insert(all.end(), t.begin(), t.end());
     }
-    int2 *dev = (int2 *)P->arena.alloc(sizeof(int2) * all.size());
-    BF_HIP(hipMemcpyAsync(dev, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, P->stream));
+    int4 *dev = (int4 *)P->arena.alloc(sizeof(int4) * all.size());
+    BF_HIP(hipMemcpyAsync(dev, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice, P->stream));
     BF_HIP(hipStreamSynchronize(P->stream));  // `all` is a host temporary
     for (int l = 0; l < P->L; ++l) P->tiles[l] = dev + off[l];
 }

@@ -87,7 +87,7 @@ void build_leaf_final(bfsft_plan *B)
         if (!active(S)) continue;
         if (S->start.s0 > 0) {
             // the state of level L - s0 goes where step s0 + 1 reads it
-            DirectDesc a = direct_desc(S->start, B->f_stage + 2 * B->f_off[t], S->tx, S->tk, S->N,
+            DirectDesc a = direct_desc(S->start, B->f_stage + 2 * B->f_off[t], S->tx, S->tk, S->N, S->tb,
                                        S->buf[S->start.s0 & 1]);
             a.first = dt;
             dp.push_back(dt);
@@ -101,6 +101,7 @@ void build_leaf_final(bfsft_plan *B)
         a.local = S->tk.local;
         a.state = S->buf[0];
         a.nleaf = S->tk.count[S->L];
+        a.shift = 0.5 * S->rho;
         a.first = lt;
         if (S->start.s0 == 0) {
             lp.push_back(lt);
@@ -113,6 +114,7 @@ void build_leaf_final(bfsft_plan *B)
         b.local = S->tx.local;
         b.bary = S->tb.bary;
         b.node_turns = S->tb.node_turns;
+        b.erot = S->tb.erot;
         b.u = B->u_stage + 2 * B->u_off[t];
         b.nx = S->nx;
         b.first = ft;

@@ -65,13 +65,18 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s,
 
 // ------------------------------------------------------------- kernels ----
 // Operator tables of one leaf width rho (Section 2.1, as interpolation rows).
+// The state is kept rotated, w^ = (E x ... x E) w with E[k] = exp(-i pi rho k / q),
+// which makes the interpolation operator of every axis real:
+//   L_t = diag(D_t) R_t diag(E),  D_t[l] = exp(i pi rho (t q + l) / (2 q)),
+// so a level is w^_out[l] = sum_s sigma^s G(s, t, l) (R_t w^_s)[l] per axis.
 struct Tables {
-    double *L64 = nullptr;   // [2][p][p] complex: Lagrange rows L_t
-    float *L32 = nullptr;
+    double *R64 = nullptr;   // [2][p][p] real: R_t
+    float *R32 = nullptr;
+    double *C64 = nullptr;   // [2 s][2 t][p] complex: G(s, t, l)
+    float *C32 = nullptr;
+    double *erot = nullptr;  // [p] complex: E[k]
+    double *L64 = nullptr;   // [2][p][p] complex: Lagrange rows L_t (matrix-core tables)
     double *PH64 = nullptr;  // [2][p] complex: phase of a child at offset s = 1
-    float *PH32 = nullptr;
-    double *LP64 = nullptr;  // [2][p][p] complex: PH_t[l] * L_t[l][l'] (rows of a child at s = 1)
-    float *LP32 = nullptr;
     double *nodes = nullptr; // [p] complex  Z_k (unused by kernels; kept for probes)
     double *bary = nullptr;  // [p] complex  barycentric weights of the nodes
     double *node_turns = nullptr; // [p] real  rho*k/q^2
@@ -90,7 +95,7 @@ struct LevelArgs {
     const uint64_t *x_keys;  // T_X level L-l keys (child position t)
     const int32_t *k_cb;     // T_K level l: children range in level l+1
     const uint64_t *k_keys;  // T_K level l+1 keys (child position s)
-    const int2 *tiles;       // [ntile] b ranges
+    const int4 *tiles;       // [ntile] (b0, b1, first child, end of children)
     int ntile;
     int cost_max;            // most LDS blocks any tile needs (translate_tile_cost)
     int rows;                // rows a' per work-group
@@ -127,6 +132,7 @@ struct LeafDesc {
     const double *local;
     void *state;
     int64_t nleaf;
+    double shift;  // rho / 2: the leaf phase is taken from B's centre (rotated state)
     int64_t first;
 };
 
@@ -136,6 +142,7 @@ struct FinalDesc {
     const double *local;
     const double *bary;
     const double *node_turns;
+    const double *erot;
     double *u;
     int64_t nx;
     int64_t first;
@@ -173,11 +180,12 @@ struct DirectDesc {
     const double *sloc;
     const double2 *sstep;
     const double2 *f;           // sources, original order
+    const double2 *erot;        // [p] E[k] of the state rotation
     void *state;                // output state of level L - s0
     int64_t first;              // first flat item (batched)
 };
 DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, const Tree &tk, int64_t N,
-                       void *state);
+                       const Tables &tb, void *state);
 int64_t direct_items(int d, int p, const DirectDesc &dd);
 void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t *prefix, int n, int64_t total);
 

@@ -27,6 +27,13 @@ template <typename V> __device__ __forceinline__ void cfma(V &acc, const V a, co
     acc.y = fma(a.y, b.x, acc.y);
 }
 
+// acc += r * b for a real r
+template <typename R, typename V> __device__ __forceinline__ void rfma(V &acc, const R r, const V b)
+{
+    acc.x = fma(r, b.x, acc.x);
+    acc.y = fma(r, b.y, acc.y);
+}
+
 template <typename V> __device__ __forceinline__ V czero()
 {
     V r;

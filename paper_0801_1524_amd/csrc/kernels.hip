@@ -24,6 +24,17 @@
 //    local offset x' = x - rho i_A.
 // No inverse of the Vandermonde matrix G (cond ~ 3e8 at p = 9) is formed.
 //
+// Rotation.  Nodes and check points lie on the unit circle, where
+// ell_k(Y) = exp(i q (arg Y - arg Z_k) / 2) times a real product of sines, so
+// L_t = diag(D_t) R_t diag(E) with R_t real, E[k] = exp(-i pi rho k / q) and
+// D_t[l] = exp(i pi rho (t q + l) / (2 q)).  Every kernel therefore keeps the
+// rotated state w^ = (E x ... x E) w, which is B's check potential with the
+// phase of B's centre (not its corner) divided out, up to a factor of A:
+// the leaf sums take offsets from the centre, the start-level direct sums
+// multiply by E, the translations apply the real R_t with the phases
+// G(s, t, l) = E[l] D_t[l] f(s, t, l) on the outputs, and the evaluation
+// folds conj(E) into its weights.
+//
 // The sweep of one level is a streaming pass: for a parent a' of T_X and a
 // tile of boxes b of T_K, the children of b are contiguous in the input row
 // a' (Morton order), and the outputs are rows a = children of a'.
@@ -68,9 +79,17 @@ __device__ double2 diff_unit(double amb, double apb)
 // ---------------------------------------------------------------- tables --
 
 // One thread block, FP64.  rho = N / 2^L; all turns are exact rationals
-// N n / (2 q^2 2^L) rounded once.
-__global__ void k_tables(int p, int64_t N, int L, double2 *L64, float2 *L32, double2 *PH64,
-                         float2 *PH32, double2 *LP64, float2 *LP32, double2 *nodes, double2 *bary,
+// N n / (2 q^2 2^L) (or N n / (4 q 2^L)) rounded once.
+//   L64  Lagrange rows L_t[l][k] = ell_k(exp(i pi rho (t q + l) / q^2)),
+//   R64  their real factor: for points on the unit circle
+//        ell_k(Y) = exp(i q (arg Y - arg Z_k) / 2) prod_{j != k} sin((arg Y - arg Z_j) / 2)
+//                                                       / sin((arg Z_k - arg Z_j) / 2),
+//        so R_t[l][k] is the sine product, taken directly,
+//   C64  G(0, t, l) = E[l] D_t[l] = exp(i pi rho (t q - l) / (2 q)) and
+//        G(1, t, l) = G(0, t, l) exp(i pi rho (t q + l) / q),
+//   erot E[k] = exp(-i pi rho k / q).
+__global__ void k_tables(int p, int64_t N, int L, double2 *L64, double2 *PH64, double *R64, float *R32,
+                         double2 *C64, float2 *C32, double2 *erot, double2 *nodes, double2 *bary,
                          double *node_turns)
 {
     const int q = p - 1;
@@ -91,6 +110,7 @@ __global__ void k_tables(int p, int64_t N, int L, double2 *L64, float2 *L32, dou
         bary[k] = lam[k];
         nodes[k] = expi_ratio(N * (int64_t)(2 * k), (int64_t)(2 * q * q) << L);
         node_turns[k] = (double)(N * (int64_t)k) / ldexp((double)(q * q), L);
+        erot[k] = expi_ratio(-N * (int64_t)k, (int64_t)(2 * q) << L);
     }
     __syncthreads();
     if (tid < 2 * p) {
@@ -109,22 +129,31 @@ __global__ void k_tables(int p, int64_t N, int L, double2 *L64, float2 *L32, dou
         }
         for (int k = 0; k < p; ++k) {
             double2 v;
-            if (exact >= 0)
+            double r = 0.0;
+            if (exact >= 0) {
                 v = make_double2(k == exact ? 1.0 : 0.0, 0.0);
-            else
+                r = k == exact ? 1.0 : 0.0;
+            } else {
                 v = ddiv(w[k], sum);
+                r = 1.0;
+                for (int j = 0; j < p; ++j) {
+                    if (j == k) continue;
+                    r *= sinpi((double)(N * (int64_t)(num - 2 * j)) / den) /
+                         sinpi((double)(N * (int64_t)(2 * k - 2 * j)) / den);
+                }
+            }
             L64[(t * p + l) * p + k] = v;
-            L32[(t * p + l) * p + k] = make_float2((float)v.x, (float)v.y);
+            R64[(t * p + l) * p + k] = r;
+            R32[(t * p + l) * p + k] = (float)r;
         }
         // phase of the child at offset s = 1: exp(i pi rho (t q + l) / q)
-        const double2 ph = expi_ratio(N * (int64_t)num, (int64_t)(2 * q) << L);
-        PH64[t * p + l] = ph;
-        PH32[t * p + l] = make_float2((float)ph.x, (float)ph.y);
-        for (int k = 0; k < p; ++k) {
-            const double2 v = dmul(ph, L64[(t * p + l) * p + k]);
-            LP64[(t * p + l) * p + k] = v;
-            LP32[(t * p + l) * p + k] = make_float2((float)v.x, (float)v.y);
-        }
+        PH64[t * p + l] = expi_ratio(N * (int64_t)num, (int64_t)(2 * q) << L);
+        const double2 g0 = expi_ratio(N * (int64_t)(t * q - l), (int64_t)(4 * q) << L);
+        const double2 g1 = expi_ratio(N * (int64_t)(3 * t * q + l), (int64_t)(4 * q) << L);
+        C64[t * p + l] = g0;
+        C64[(2 + t) * p + l] = g1;
+        C32[t * p + l] = make_float2((float)g0.x, (float)g0.y);
+        C32[(2 + t) * p + l] = make_float2((float)g1.x, (float)g1.y);
     }
 }
 
@@ -145,12 +174,14 @@ __global__ void k_sigma(const uint64_t *__restrict__ keys, int64_t n, int d, int
 // ------------------------------------------------------------------ leaf --
 
 // Step 2: w^{A0 B}_l = sum_{k_j in B} exp(2 pi i l . k'_j / q) f_j for every
-// leaf B of T_K (A0 = root of T_X).  One thread per (leaf, grid point).
+// leaf B of T_K (A0 = root of T_X), stored rotated: E[l_a] = exp(-2 pi i
+// l_a (rho / 2) / q) per axis turns the offset k' from B's corner into the
+// offset k' - rho / 2 from its centre.  One thread per (leaf, grid point).
 template <int D, typename S>
 __device__ __forceinline__ void leaf_item(int p, int64_t nleaf, const double2 *__restrict__ f,
                                           const int32_t *__restrict__ perm,
                                           const int32_t *__restrict__ beg,
-                                          const double *__restrict__ local,
+                                          const double *__restrict__ local, double shift,
                                           typename CV<S>::t *__restrict__ state, int64_t gid)
 {
     int PD = p;
@@ -171,7 +202,7 @@ __device__ __forceinline__ void leaf_item(int p, int64_t nleaf, const double2 *_
     for (int t = beg[b]; t < beg[b + 1]; ++t) {
         const int j = perm[t];
         double turns = 0.0;
-        for (int a = 0; a < D; ++a) turns = fma((double)lidx[a], local[(int64_t)j * D + a], turns);
+        for (int a = 0; a < D; ++a) turns = fma((double)lidx[a], local[(int64_t)j * D + a] - shift, turns);
         double s, c;
         sincospi(2.0 * turns * invq, &s, &c);
         const double2 fj = f[j];
@@ -189,10 +220,10 @@ __global__ __launch_bounds__(256) void k_leaf(int p, int64_t nleaf,
                                              const double2 *__restrict__ f,
                                              const int32_t *__restrict__ perm,
                                              const int32_t *__restrict__ beg,
-                                             const double *__restrict__ local,
+                                             const double *__restrict__ local, double shift,
                                              typename CV<S>::t *__restrict__ state)
 {
-    leaf_item<D, S>(p, nleaf, f, perm, beg, local, state, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    leaf_item<D, S>(p, nleaf, f, perm, beg, local, shift, state, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------- start level --
@@ -321,15 +352,27 @@ __device__ __forceinline__ void direct_item(const DirectDesc &dd, int64_t gid)
             e = cmul(e, rl);
         }
     }
+    // rotated state: times E[l_a] of every axis.  All factors are read
+    // before the first store (the table could alias the state for all the
+    // compiler knows); the uniform ones through scalar loads.
     typename CV<S>::t *o = (typename CV<S>::t *)dd.state + ab * PD + ((int64_t)l_outer * P + lg0) * P;
+    const cptr<double> er = (cptr<double>)(const void *)dd.erot;
+    double2 el[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) el[l] = ldc<double2>(er, l);
+    const double2 eo = D == 3 ? dd.erot[l_outer] : make_double2(1.0, 0.0);
+    double2 eg[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) eg[g] = cmul(eo, lg0 + g < P ? dd.erot[lg0 + g] : make_double2(1.0, 0.0));
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (lg0 + g >= P) break;
 #pragma unroll
         for (int l = 0; l < P; ++l) {
+            const double2 r = cmul(acc[g][l], cmul(eg[g], el[l]));
             typename CV<S>::t v;
-            v.x = (S)acc[g][l].x;
-            v.y = (S)acc[g][l].y;
+            v.x = (S)r.x;
+            v.y = (S)r.y;
             o[g * P + l] = v;
         }
     }
@@ -360,7 +403,7 @@ __global__ __launch_bounds__(256) void k_leaf_batched(int p, const LeafDesc *__r
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const LeafDesc &d = ds[owner(prefix, n, i)];
-    leaf_item<D, S>(p, d.nleaf, (const double2 *)d.f, d.perm, d.beg, d.local,
+    leaf_item<D, S>(p, d.nleaf, (const double2 *)d.f, d.perm, d.beg, d.local, d.shift,
                     (typename CV<S>::t *)d.state, i - d.first);
 }
 
@@ -378,13 +421,15 @@ __global__ __launch_bounds__(256) void k_direct_batched(const DirectDesc *__rest
 // ----------------------------------------------------------------- final --
 
 // Step 4: u_i = sum_l prod_a ell_{l_a}(exp(2 pi i x'_{i,a} / q)) w^{A B0}_l for
-// x_i in leaf A of T_X (barycentric Lagrange interpolation).
+// x_i in leaf A of T_X (barycentric Lagrange interpolation); the state is
+// rotated, w = conj(E x ... x E) w^, so each weight takes conj(E[l_a]).
 template <int D, int P, typename S>
 __device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *__restrict__ state,
                                            const int32_t *__restrict__ leaf_of,
                                            const double *__restrict__ local,
                                            const double2 *__restrict__ bary,
                                            const double *__restrict__ node_turns,
+                                           const double2 *__restrict__ erot,
                                            double2 *__restrict__ u, int64_t i)
 {
     if (i >= nx) return;
@@ -405,8 +450,10 @@ __device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *
             sum.y += w.y;
         }
 #pragma unroll
-        for (int k = 0; k < P; ++k)
-            ell[a][k] = exact >= 0 ? make_double2(k == exact ? 1.0 : 0.0, 0.0) : ddiv(ell[a][k], sum);
+        for (int k = 0; k < P; ++k) {
+            const double2 e = make_double2(erot[k].x, -erot[k].y);
+            ell[a][k] = exact >= 0 ? (k == exact ? e : make_double2(0.0, 0.0)) : cmul(ddiv(ell[a][k], sum), e);
+        }
     }
     constexpr int PD = (D == 2) ? P * P : P * P * P;
     const typename CV<S>::t *w = state + (int64_t)leaf_of[i] * PD;
@@ -441,9 +488,10 @@ __global__ __launch_bounds__(256) void k_final(int64_t nx, const typename CV<S>:
                                               const double *__restrict__ local,
                                               const double2 *__restrict__ bary,
                                               const double *__restrict__ node_turns,
+                                              const double2 *__restrict__ erot,
                                               double2 *__restrict__ u)
 {
-    final_item<D, P, S>(nx, state, leaf_of, local, bary, node_turns, u,
+    final_item<D, P, S>(nx, state, leaf_of, local, bary, node_turns, erot, u,
                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -456,14 +504,16 @@ __global__ __launch_bounds__(256) void k_final_batched(const FinalDesc *__restri
     if (i >= total) return;
     const FinalDesc &d = ds[owner(prefix, n, i)];
     final_item<D, P, S>(d.nx, (const typename CV<S>::t *)d.state, d.leaf_of, d.local,
-                        (const double2 *)d.bary, d.node_turns, (double2 *)d.u, i - d.first);
+                        (const double2 *)d.bary, d.node_turns, (const double2 *)d.erot, (double2 *)d.u,
+                        i - d.first);
 }
 
 // ----------------------------------------------------------------- export --
 
 // Parity probe: pot[a][b][l] = exp(2 pi i x^A_l . c^B / N) w^{AB}_l, i.e. the
-// paper's check potential u^{AB} at T_K level lvl; the phase is
-// sum_a rho i_B (q i_A + l_a) / q with the numerator reduced exactly.
+// paper's check potential u^{AB} at T_K level lvl, from the rotated state
+// w^ = E w; the phase is sum_a [rho i_B (q i_A + l_a) / q + rho l_a / (2 q)]
+// turns, its numerator over 2 q 2^L reduced exactly.
 template <typename S>
 __global__ void k_export(int d, int p, const typename CV<S>::t *__restrict__ st,
                          const uint64_t *__restrict__ xkeys, int64_t nA,
@@ -480,6 +530,8 @@ __global__ void k_export(int d, int p, const typename CV<S>::t *__restrict__ st,
     const int q = p - 1;
     const uint64_t D = (uint64_t)q << L;
     const uint64_t Nm = (uint64_t)N % D;
+    const uint64_t D2 = 2 * D;
+    const uint64_t N2 = (uint64_t)N % D2;
     const int mA = L - lvl;
     uint64_t tot = 0;
     int r = e;
@@ -495,8 +547,10 @@ __global__ void k_export(int d, int p, const typename CV<S>::t *__restrict__ st,
         const uint64_t n = (cB * ((uint64_t)q * cA + (uint64_t)lix[a])) % D;
         tot = (tot + (Nm * n) % D) % D;
     }
+    uint64_t tot2 = 2 * tot;
+    for (int a = 0; a < d; ++a) tot2 = (tot2 + N2 * (uint64_t)lix[a]) % D2;
     double s, c;
-    sincospi(2.0 * (double)tot / (double)D, &s, &c);
+    sincospi(2.0 * (double)tot2 / (double)D2, &s, &c);
     const double2 w = cvt<double2>(st[gid]);
     pot[gid] = make_double2(c * w.x - s * w.y, c * w.y + s * w.x);
 }
@@ -525,17 +579,18 @@ inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 void build_tables(Tables &tb, int p, int64_t N, int L, Arena &arena, hipStream_t s)
 {
+    tb.R64 = (double *)arena.alloc(sizeof(double) * 2 * p * p);
+    tb.R32 = (float *)arena.alloc(sizeof(float) * 2 * p * p);
+    tb.C64 = (double *)arena.alloc(sizeof(double2) * 4 * p);
+    tb.C32 = (float *)arena.alloc(sizeof(float2) * 4 * p);
+    tb.erot = (double *)arena.alloc(sizeof(double2) * p);
     tb.L64 = (double *)arena.alloc(sizeof(double2) * 2 * p * p);
-    tb.L32 = (float *)arena.alloc(sizeof(float2) * 2 * p * p);
     tb.PH64 = (double *)arena.alloc(sizeof(double2) * 2 * p);
-    tb.PH32 = (float *)arena.alloc(sizeof(float2) * 2 * p);
-    tb.LP64 = (double *)arena.alloc(sizeof(double2) * 2 * p * p);
-    tb.LP32 = (float *)arena.alloc(sizeof(float2) * 2 * p * p);
     tb.nodes = (double *)arena.alloc(sizeof(double2) * p);
     tb.bary = (double *)arena.alloc(sizeof(double2) * p);
     tb.node_turns = (double *)arena.alloc(sizeof(double) * p);
-    k_tables<<<1, 64, 0, s>>>(p, N, L, (double2 *)tb.L64, (float2 *)tb.L32, (double2 *)tb.PH64,
-                              (float2 *)tb.PH32, (double2 *)tb.LP64, (float2 *)tb.LP32,
+    k_tables<<<1, 64, 0, s>>>(p, N, L, (double2 *)tb.L64, (double2 *)tb.PH64, tb.R64, tb.R32,
+                              (double2 *)tb.C64, (float2 *)tb.C32, (double2 *)tb.erot,
                               (double2 *)tb.nodes, (double2 *)tb.bary, tb.node_turns);
     BF_HIP(hipGetLastError());
     if (p >= 5 && p <= 9) {
@@ -577,7 +632,7 @@ void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rh
 constexpr int kDirectG = 3;  // grid lines per thread of the direct sums
 
 DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, const Tree &tk, int64_t N,
-                       void *state)
+                       const Tables &tb, void *state)
 {
     DirectDesc d;
     d.s0 = st.s0;
@@ -593,6 +648,7 @@ DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, co
     d.sloc = st.sloc;
     d.sstep = st.sratio;
     d.f = (const double2 *)f;
+    d.erot = (const double2 *)tb.erot;
     d.state = state;
     d.first = 0;
     return d;
@@ -607,7 +663,7 @@ int64_t direct_items(int d, int p, const DirectDesc &dd)
 void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
                    int64_t N, void *state)
 {
-    const DirectDesc dd = direct_desc(st, f, tx, tk, N, state);
+    const DirectDesc dd = direct_desc(st, f, tx, tk, N, *c.tb, state);
     const int64_t n = direct_items(c.d, c.p, dd);
     if (n == 0) return;
     const bool f32 = c.precision != BFSFT_FP64;
@@ -646,7 +702,7 @@ void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t 
     BF_HIP(hipGetLastError());
 }
 
-void launch_leaf(const Launch &c, const double *f, const Tree &tk, double, void *state)
+void launch_leaf(const Launch &c, const double *f, const Tree &tk, double rho, void *state)
 {
     const int64_t nl = tk.count[tk.L];
     int PD = c.p;
@@ -654,20 +710,21 @@ void launch_leaf(const Launch &c, const double *f, const Tree &tk, double, void 
     const int64_t n = nl * PD;
     if (n == 0) return;
     const bool f32 = c.precision != BFSFT_FP64;
+    const double sh = 0.5 * rho;
     if (c.d == 2) {
         if (f32)
             k_leaf<2, float><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
-                                                               tk.leaf_beg, tk.local, (float2 *)state);
+                                                               tk.leaf_beg, tk.local, sh, (float2 *)state);
         else
             k_leaf<2, double><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
-                                                                tk.leaf_beg, tk.local, (double2 *)state);
+                                                                tk.leaf_beg, tk.local, sh, (double2 *)state);
     } else {
         if (f32)
             k_leaf<3, float><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
-                                                               tk.leaf_beg, tk.local, (float2 *)state);
+                                                               tk.leaf_beg, tk.local, sh, (float2 *)state);
         else
             k_leaf<3, double><<<nblk(n, 256), 256, 0, c.stream>>>(c.p, nl, (const double2 *)f, tk.perm,
-                                                                tk.leaf_beg, tk.local, (double2 *)state);
+                                                                tk.leaf_beg, tk.local, sh, (double2 *)state);
     }
     BF_HIP(hipGetLastError());
 }
@@ -682,20 +739,20 @@ void launch_final(const Launch &c, const void *state, const Tree &tx, double, in
             if (f32)
                 k_final<2, P, float><<<nblk(nx, 256), 256, 0, c.stream>>>(
                     nx, (const float2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
-                    c.tb->node_turns, (double2 *)u);
+                    c.tb->node_turns, (const double2 *)c.tb->erot, (double2 *)u);
             else
                 k_final<2, P, double><<<nblk(nx, 256), 256, 0, c.stream>>>(
                     nx, (const double2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
-                    c.tb->node_turns, (double2 *)u);
+                    c.tb->node_turns, (const double2 *)c.tb->erot, (double2 *)u);
         } else if constexpr (P <= 8) {
             if (f32)
                 k_final<3, P, float><<<nblk(nx, 256), 256, 0, c.stream>>>(
                     nx, (const float2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
-                    c.tb->node_turns, (double2 *)u);
+                    c.tb->node_turns, (const double2 *)c.tb->erot, (double2 *)u);
             else
                 k_final<3, P, double><<<nblk(nx, 256), 256, 0, c.stream>>>(
                     nx, (const double2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
-                    c.tb->node_turns, (double2 *)u);
+                    c.tb->node_turns, (const double2 *)c.tb->erot, (double2 *)u);
         } else {
             throw Error{BFSFT_EINVAL, "p > 8 in 3D"};
         }

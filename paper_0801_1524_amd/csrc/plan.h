@@ -24,7 +24,7 @@ struct bfsft_plan {
     bool valu_only = false;             // member of a batched plan (its kernel is the VALU one)
     bfsft_plan *adj = nullptr;          // adjoint: trees exchanged, built on first use
     double *adj_in = nullptr;           // adjoint plan: conjugated input staging [nk] complex
-    std::vector<int2 *> tiles;          // per T_K level l = 0..L-1 (output level of the step)
+    std::vector<int4 *> tiles;          // per T_K level l = 0..L-1 (output level of the step)
     std::vector<int> ntile;
     std::vector<int> cost_max;          // most LDS blocks a tile of level l needs
     std::vector<int> rows;              // rows a' per work-group at level l

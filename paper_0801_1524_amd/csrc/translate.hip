@@ -2,28 +2,40 @@
 //
 // For a box pair (A, B) at T_K level l, A = child t of A' and B with
 // children B_s, the state (B's check potential at A's check points, B's
-// corner phase divided out) is, per axis, interpolated from the children's
-// states (see kernels.hip for the derivation):
+// corner phase divided out; see kernels.hip for the derivation) is, per
+// axis, interpolated from the children's states:
 //
 //   w^{AB}[l] = sum_s f(s, t, l) * (L_t w^{A'B_s})[l],
 //   f(0, t, l) = 1,   f(1, t, l) = sigma_{A'} exp(i pi rho (t q + l) / q),
 //   L_t[l][l'] = ell_{l'}( exp(i pi rho (t q + l) / q^2) ).
 //
-// The check point (t + l/q)/2 of A coincides with the node (t q + l)/2 / q of
-// A' whenever t q + l is even; those rows of L_t are unit vectors, so about
-// half of every 1D interpolation is a copy and only the other rows are dot
-// products (4 of 9 at p = 9).  Which rows are copies depends only on (p, t),
-// so it is resolved at compile time.
+// The nodes and the targets of this interpolation lie on the unit circle,
+// where the Lagrange basis is a phase times a real product of sines:
+// L_t = diag(D_t) R_t diag(E) with R_t real and E[k] = exp(-i pi rho k / q).
+// The state is therefore kept rotated, w^ = (E x E) w, and a level is
+//
+//   w^{AB}[l] = sum_s sigma^s G(s, t, l) (R_t w^{A'B_s})[l],
+//   G(0, t, l) = exp(i pi rho (t q - l) / (2 q)),
+//   G(1, t, l) = G(0, t, l) exp(i pi rho (t q + l) / q),
+//
+// so every contraction multiplies complex state by a real operator (two
+// FMAs per term instead of four) and the phases are applied once per
+// output.  The check point (t + l/q)/2 of A coincides with the node
+// (t q + l)/2 / q of A' whenever t q + l is even; those rows of R_t are unit
+// vectors, so about half of every 1D interpolation is a copy and only the
+// other rows are dot products (4 of 9 at p = 9).  Which rows are copies
+// depends only on (p, t), so it is resolved at compile time.
 //
 // Work decomposition.  A work-group takes R consecutive rows a' of T_X level
 // L-l-1 and one tile of boxes b of T_K level l; the children of the tile are
 // a contiguous range of every input row (Morton order), and the outputs are
 // the rows a = children of each a'.  Per output position t2 along axis 2:
-//   stage 1: one thread per input row (a', j, l): Y = L_t2 along axis 2,
+//   stage 1: one thread per input row (a', j, l): Y = R_t2 along axis 2,
 //   stage 2: one thread per output column (a', b, m): sum the children with
-//            the same s1, apply L_t1 along axis 1, write the column.
-// The interpolation operator of each stage depends only on t, so it is
-// uniform across the work-group and read through scalar loads.
+//            the same s1, each times its G(s2, t2, m), apply R_t1 along
+//            axis 1, combine the two sums with G(s1, t1, .) and write.
+// The operators of each stage depend only on t, so they are uniform across
+// the work-group and read through scalar loads.
 #include "bfsft_impl.h"
 #include "cplx.h"
 #include "dispatch.h"
@@ -40,123 +52,92 @@ namespace {
 
 using namespace tr;
 
-// phase of a child at offset 1 along an axis, output index l, position t:
-// sigma_{A'} * PH_t[l]; sigma = 1 when rho = 1 (RHO1)
-template <bool RHO1, typename Cv, typename C>
-__device__ __forceinline__ Cv child_phase(cptr<C> PH, int t, int l, int P, const Cv sg)
+// coefficient G(s, t, l) of the table [2 s][2 t][P]
+template <typename Cv, typename C>
+__device__ __forceinline__ Cv gcoef(cptr<C> Ct, int s, int t, int l, int P)
 {
-    const Cv ph = ldc<Cv>(PH, t * P + l);
-    return RHO1 ? ph : cmul(sg, ph);
+    return ldc<Cv>(Ct, (2 * s + t) * P + l);
 }
 
-// stage 1 for one input row x and one output position T2 along axis 2
-template <int P, int T2, bool RHO1, typename C, typename Yv>
-__device__ __forceinline__ void row_interp(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *x,
-                                           bool s2, const typename CV<C>::t sg, Yv *dst)
+// stage 1 for one input row x and one output position T2: the dot rows of
+// R_t2 and the copy rows; no phases
+template <int P, int T2, typename C, typename Yv>
+__device__ __forceinline__ void row_interp(cptr<C> Rt, const typename CV<C>::t *x, Yv *dst)
 {
     using Cv = typename CV<C>::t;
     using RW = Rows<P, T2>;
     constexpr int PP = P * P, Q = P - 1;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < RW::ndot; ++k) {
         const int m = RW::first_dot + 2 * k;
         Cv y = czero<Cv>();
 #pragma unroll
-        for (int mp = 0; mp < P; ++mp) cfma(y, ldc<Cv>(Lt, T2 * PP + m * P + mp), x[mp]);
-        if (s2) y = cmul(y, child_phase<RHO1, Cv>(PH, T2, m, P, sg));
+        for (int mp = 0; mp < P; ++mp) rfma(y, Rt[T2 * PP + m * P + mp], x[mp]);
         st(dst + m, y);
     }
 #pragma unroll
     for (int m = 0; m < P; ++m) {
         if (!RW::copy(m)) continue;
-        Cv y = x[(T2 * Q + m) / 2];
-        if (s2) y = cmul(y, child_phase<RHO1, Cv>(PH, T2, m, P, sg));
-        st(dst + m, y);
+        st(dst + m, x[(T2 * Q + m) / 2]);
     }
 }
 
-// Output column of stage 2 (2D) at position T1, restricted to the output
-// rows of group g of G (dot rows k = g, g+G, ... and every G-th copy row; g
-// is uniform across the wave).  z0 sums the children at s1 = 0, z1 those at
-// s1 = 1 with sigma_{A'} of axis 1 already applied, so the s1 = 1 rows use
-// the folded table LP = diag(PH_t) L_t and every dot row is one accumulator.
-template <int P, int T1, typename S, typename C>
-__device__ __forceinline__ void col_interp_g(cptr<C> Lt, cptr<C> LP, cptr<C> PH,
-                                             const typename CV<C>::t *z0,
-                                             const typename CV<C>::t *z1, bool h1,
-                                             typename CV<S>::t *dst, int g, int G)
+// One output line at position T along the contracted axis, written with
+// stride `stride` to a destination of element type Dv (LDS or HBM):
+//   o[l] = G(0, T, l) (R_T z0)[l] + G(1, T, l) (R_T z1)[l],
+// z1 carrying sigma already.  Only the output rows of group g of G are
+// written (dot rows k = g, g + G, ... and every G-th copy row; g is uniform
+// across the wave); G = 1 writes the whole line.
+template <int P, int T, typename C, typename Dv, bool ONE = false>
+__device__ __forceinline__ void line_interp(cptr<C> Rt, cptr<C> Ct, const typename CV<C>::t *z0,
+                                            const typename CV<C>::t *z1, Dv *dst, int stride, int g,
+                                            int G)
 {
     using Cv = typename CV<C>::t;
-    using RW = Rows<P, T1>;
+    using RW = Rows<P, T>;
     constexpr int PP = P * P, Q = P - 1;
-#pragma unroll 1
+    if (ONE) {
+        g = 0;
+        G = 1;
+    }
+#pragma unroll
     for (int k = g; k < RW::ndot; k += G) {
         const int l = RW::first_dot + 2 * k;
-        Cv o = czero<Cv>();
+        Cv a = czero<Cv>(), b = czero<Cv>();
 #pragma unroll
         for (int lp = 0; lp < P; ++lp) {
-            cfma(o, ldc<Cv>(Lt, T1 * PP + l * P + lp), z0[lp]);
-            cfma(o, ldc<Cv>(LP, T1 * PP + l * P + lp), z1[lp]);
+            const auto r = Rt[T * PP + l * P + lp];
+            rfma(a, r, z0[lp]);
+            rfma(b, r, z1[lp]);
         }
-        st(dst + l * P, o);
+        Cv o = cmul(gcoef<Cv>(Ct, 0, T, l, P), a);
+        cfma(o, gcoef<Cv>(Ct, 1, T, l, P), b);
+        st(dst + l * stride, o);
     }
 #pragma unroll
     for (int l = 0; l < P; ++l) {
         if (!RW::copy(l)) continue;
         if (RW::copy_index(l) % G != g) continue;
-        Cv o = z0[(T1 * Q + l) / 2];
-        if (h1) o = cadd(o, cmul(z1[(T1 * Q + l) / 2], ldc<Cv>(PH, T1 * P + l)));
-        st(dst + l * P, o);
-    }
-}
-
-// Y element type: the state precision for the FP32-state paths, FP64 otherwise
-#ifdef BFSFT_MIXED_Y64
-template <typename S, typename C> struct YT { using t = typename CV<C>::t; };
-#else
-template <typename S, typename C> struct YT { using t = typename CV<S>::t; };
-#endif
-
-// Strided variant of col_interp: the output column has stride `stride`
-// elements and goes to a destination of element type Dv (LDS or HBM).
-template <int P, int T, bool RHO1, typename C, typename Dv>
-__device__ __forceinline__ void col_interp_s(cptr<C> Lt, cptr<C> PH, const typename CV<C>::t *z0,
-                                             const typename CV<C>::t *z1, bool h1,
-                                             const typename CV<C>::t sg, Dv *dst, int stride)
-{
-    using Cv = typename CV<C>::t;
-    using RW = Rows<P, T>;
-    constexpr int PP = P * P, Q = P - 1;
-#pragma unroll 1
-    for (int k = 0; k < RW::ndot; ++k) {
-        const int l = RW::first_dot + 2 * k;
-        Cv o0 = czero<Cv>(), o1 = czero<Cv>();
-#pragma unroll
-        for (int lp = 0; lp < P; ++lp) {
-            const Cv lv = ldc<Cv>(Lt, T * PP + l * P + lp);
-            cfma(o0, lv, z0[lp]);
-            cfma(o1, lv, z1[lp]);
-        }
-        if (h1) o0 = cadd(o0, cmul(o1, child_phase<RHO1, Cv>(PH, T, l, P, sg)));
-        st(dst + l * stride, o0);
-    }
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-        if (!RW::copy(l)) continue;
-        Cv o = z0[(T * Q + l) / 2];
-        if (h1) o = cadd(o, cmul(z1[(T * Q + l) / 2], child_phase<RHO1, Cv>(PH, T, l, P, sg)));
+        const int n = (T * Q + l) / 2;
+        Cv o = cmul(gcoef<Cv>(Ct, 0, T, l, P), z0[n]);
+        cfma(o, gcoef<Cv>(Ct, 1, T, l, P), z1[n]);
         st(dst + l * stride, o);
     }
 }
 
+// Y element type: the state precision for the FP32-state paths, FP64 otherwise
+template <typename S, typename C> struct YT { using t = typename CV<S>::t; };
+
 // Step 3, 3D (octrees, p^3 grids, axis 0 = l slowest, axis 2 = n fastest).
 // Child positions s and output positions t carry the parity of axis a in bit
 // a.  Per output position (t2 along axis 2, then t1 along axis 1):
-//   stage 1 (axis 2): rows (j, l, m):  Y1 = L_t2 along n, phase of bit 2,
-//   stage 2 (axis 1): lines (b, e0, l, n): sum the children over bit 2,
-//                     Y2[b][e0] = sum over bit 1 of phase * L_t1 along m,
-//   stage 3 (axis 0): lines (b, m, n): out_t = sum over bit 0 of phase *
-//                     L_t0 along l, written to HBM.
+//   stage 1 (axis 2): rows (j, l, m):  Y1 = R_t2 along n,
+//   stage 2 (axis 1): lines (b, e0, l, n): sum the children over bit 2, each
+//                     times G(e2, t2, n) (and sigma of axis 2 for e2 = 1),
+//                     then Y2[b][e0] = sum over bit 1 of G(e1, t1, .) R_t1
+//                     along m,
+//   stage 3 (axis 0): lines (b, m, n): out_t = sum over bit 0 of
+//                     G(e0, t0, .) R_t0 along l, written to HBM.
 template <int P, bool RHO1, typename S, typename C>
 __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, unsigned char *smem)
 {
@@ -168,21 +149,19 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     __shared__ int s_bits[kRowsMax];  // bit t: output t; bit 8+t2: some output with t2;
                                       // bit 16 + 2*t2 + t1: some output with (t1, t2)
     __shared__ Cv s_sig[kRowsMax * 3];
-    __shared__ unsigned char s_pos[kInMax];
     __shared__ signed char s_cj[kInMax * 8];
 
     const int64_t g = gid / a.ntile;
     const int tile = (int)(gid - g * a.ntile);
     const int64_t ap0 = g * a.rows;
     const int R = (int)min((int64_t)a.rows, a.nap - ap0);
-    const int2 bt = a.tiles[tile];
+    const int4 bt = a.tiles[tile];
     const int b0 = bt.x, nb = bt.y - bt.x;
-    const int J0 = a.k_cb[b0];
-    const int nin = a.k_cb[bt.y] - J0;
+    const int J0 = bt.z;
+    const int nin = bt.w - bt.z;
     Yv *Y1 = reinterpret_cast<Yv *>(smem);  // [R][nin][P3]
     Yv *Y2 = Y1 + R * nin * P3;             // [R][nb][2][P3]
 
-    for (int i = threadIdx.x; i < nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[J0 + i] & 7);
     for (int bl = threadIdx.x; bl < nb; bl += kTT) {
         signed char cj[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
         for (int j = a.k_cb[b0 + bl]; j < a.k_cb[b0 + bl + 1]; ++j)
@@ -213,8 +192,8 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     int all = 0;
     for (int r = 0; r < R; ++r) all |= s_bits[r];
 
-    const cptr<C> Lt = (cptr<C>)(a.Lt);
-    const cptr<C> PH = (cptr<C>)(a.PH);
+    const cptr<C> Rt = (cptr<C>)(a.R);
+    const cptr<C> Ct = (cptr<C>)(a.C);
     for (int t2 = 0; t2 < 2; ++t2) {
         if (!(all & (1 << (8 + t2)))) continue;
         // stage 1
@@ -222,18 +201,15 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
             if (!(s_bits[r] & (1 << (8 + t2)))) continue;
             const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * P3;
             Yv *Yr = Y1 + r * nin * P3;
-            const Cv sg = s_sig[r * 3 + 2];
             for (int v = threadIdx.x; v < nin * P2; v += kTT) {
-                const int j = v / P2;
                 const Sv *src = in + v * P;
                 Cv x[P];
 #pragma unroll
                 for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
-                const bool e2 = (s_pos[j] >> 2) & 1;
                 if (t2 == 0)
-                    row_interp<P, 0, RHO1, C>(Lt, PH, x, e2, sg, Yr + v * P);
+                    row_interp<P, 0, C>(Rt, x, Yr + v * P);
                 else
-                    row_interp<P, 1, RHO1, C>(Lt, PH, x, e2, sg, Yr + v * P);
+                    row_interp<P, 1, C>(Rt, x, Yr + v * P);
             }
         }
         __syncthreads();
@@ -244,36 +220,42 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                 if (!(s_bits[r] & (1 << (16 + 2 * t2 + t1)))) continue;
                 const Yv *Yr = Y1 + r * nin * P3;
                 Yv *Y2r = Y2 + r * nb * 2 * P3;
-                const Cv sg = s_sig[r * 3 + 1];
+                const Cv sg1 = s_sig[r * 3 + 1], sg2 = s_sig[r * 3 + 2];
                 for (int v = threadIdx.x; v < nb * 2 * P2; v += kTT) {
                     const int bl = v / (2 * P2);
                     const int rem = v - bl * 2 * P2;
                     const int e0 = rem / P2;
                     const int ln = rem - e0 * P2;
                     const int l = ln / P, n = ln - l * P;
+                    const Cv g0 = gcoef<Cv>(Ct, 0, t2, n, P);
+                    Cv g1 = gcoef<Cv>(Ct, 1, t2, n, P);
+                    if (!RHO1) g1 = cmul(g1, sg2);
                     Cv z0[P], z1[P];
 #pragma unroll
                     for (int m = 0; m < P; ++m) z0[m] = z1[m] = czero<Cv>();
-                    bool h1 = false;
 #pragma unroll
                     for (int e12 = 0; e12 < 4; ++e12) {  // e1 = bit 0 of e12, e2 = bit 1
                         const int c = s_cj[bl * 8 + e0 + 2 * e12];
                         if (c < 0) continue;
+                        const Cv gw = (e12 & 2) ? g1 : g0;
                         const Yv *yp = Yr + c * P3 + l * P2 + n;
                         if (e12 & 1) {
-                            h1 = true;
 #pragma unroll
-                            for (int m = 0; m < P; ++m) z1[m] = cadd(z1[m], ld<Cv>(yp + m * P));
+                            for (int m = 0; m < P; ++m) cfma(z1[m], gw, ld<Cv>(yp + m * P));
                         } else {
 #pragma unroll
-                            for (int m = 0; m < P; ++m) z0[m] = cadd(z0[m], ld<Cv>(yp + m * P));
+                            for (int m = 0; m < P; ++m) cfma(z0[m], gw, ld<Cv>(yp + m * P));
                         }
+                    }
+                    if (!RHO1) {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) z1[m] = cmul(z1[m], sg1);
                     }
                     Yv *dst = Y2r + (bl * 2 + e0) * P3 + l * P2 + n;
                     if (t1 == 0)
-                        col_interp_s<P, 0, RHO1, C>(Lt, PH, z0, z1, h1, sg, dst, P);
+                        line_interp<P, 0, C, Yv, true>(Rt, Ct, z0, z1, dst, P, 0, 1);
                     else
-                        col_interp_s<P, 1, RHO1, C>(Lt, PH, z0, z1, h1, sg, dst, P);
+                        line_interp<P, 1, C, Yv, true>(Rt, Ct, z0, z1, dst, P, 0, 1);
                 }
             }
             __syncthreads();
@@ -282,7 +264,7 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                 const int bits = s_bits[r];
                 if (!(bits & (1 << (16 + 2 * t2 + t1)))) continue;
                 const Yv *Y2r = Y2 + r * nb * 2 * P3;
-                const Cv sg = s_sig[r * 3 + 0];
+                const Cv sg0 = s_sig[r * 3 + 0];
                 const int ta = 4 * t2 + 2 * t1;
                 const int a0 = s_out[r * 8 + ta], a1 = s_out[r * 8 + ta + 1];
                 for (int v = threadIdx.x; v < nb * P2; v += kTT) {
@@ -298,13 +280,14 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                     for (int l = 0; l < P; ++l) {
                         z0[l] = h0 ? ld<Cv>(y0 + l * P2) : czero<Cv>();
                         z1[l] = h1 ? ld<Cv>(y1 + l * P2) : czero<Cv>();
+                        if (!RHO1) z1[l] = cmul(z1[l], sg0);
                     }
                     if (a0 >= 0)
-                        col_interp_s<P, 0, RHO1, C>(Lt, PH, z0, z1, h1, sg,
-                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2);
+                        line_interp<P, 0, C, Sv, true>(Rt, Ct, z0, z1,
+                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2, 0, 1);
                     if (a1 >= 0)
-                        col_interp_s<P, 1, RHO1, C>(Lt, PH, z0, z1, h1, sg,
-                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2);
+                        line_interp<P, 1, C, Sv, true>(Rt, Ct, z0, z1,
+                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2, 0, 1);
                 }
             }
             __syncthreads();
@@ -326,35 +309,52 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     __shared__ Cv s_sig[kRowsMax * 2];
     __shared__ unsigned char s_pos[kInMax];
     __shared__ signed char s_cj[kInMax * 4];  // [b][s]: local child index or -1
-    const Item2D it = setup2d<Cv>(a, gid, s_out, s_bits, s_sig, s_pos, s_cj);
+    Item2D it = item2d(a, gid);
     const int64_t ap0 = it.ap0;
-    const int R = it.R, b0 = it.b0, nb = it.nb, J0 = it.J0, nin = it.nin, all = it.all;
+    const int R = it.R, b0 = it.b0, nb = it.nb, J0 = it.J0, nin = it.nin;
 
-    const cptr<C> Lt = (cptr<C>)(a.Lt);
-    const cptr<C> PH = (cptr<C>)(a.PH);
-    const cptr<C> LP = (cptr<C>)(a.LP);
+    const cptr<C> Rt = (cptr<C>)(a.R);
+    const cptr<C> Ct = (cptr<C>)(a.C);
     const int ysz = R * nin * PP;  // one t2 half of Y
 
     // stage 1: every input row once, both output positions t2 it is needed
-    // for; the rows a' of the work-group are processed side by side
-    // row a' of a flat index through a float reciprocal (exact: the index
-    // is below 2^16, so the error is far below the distance 0.5 / rowlen)
+    // for; the rows a' of the work-group are processed side by side.  The
+    // row a' of a flat index comes from a float reciprocal (exact: the index
+    // is below 2^16, so the error is far below the distance 0.5 / rowlen).
+    // Each thread's next row is loaded while the current one is computed,
+    // the first one before the tables below are built.
     const int rowlen = nin * P;
+    const int nrows = R * rowlen;
     const float inv_rowlen = 1.0f / (float)rowlen;
-    for (int v = threadIdx.x; v < R * rowlen; v += kTT) {
+    const Sv *in0 = reinterpret_cast<const Sv *>(a.in) + (ap0 * a.in_row + J0) * PP;
+    const int64_t in_rs = a.in_row * PP;
+    auto row_src = [&](int v) {
+        const int r = (int)(((float)v + 0.5f) * inv_rowlen);
+        return in0 + r * in_rs + (v - r * rowlen) * P;
+    };
+    Sv xn[P];
+    if ((int)threadIdx.x < nrows) {
+        const Sv *src = row_src(threadIdx.x);
+#pragma unroll
+        for (int m = 0; m < P; ++m) xn[m] = src[m];
+    }
+    tables2d<Cv>(a, it, s_out, s_bits, s_sig, s_pos, s_cj);
+    const int all = it.all;
+    for (int v = threadIdx.x; v < nrows; v += kTT) {
         const int r = (int)(((float)v + 0.5f) * inv_rowlen);
         const int w = v - r * rowlen;
-        const int j = w / P;
         const int bits = s_bits[r];
-        const Sv *src = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * PP + w * P;
         Cv x[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
-        const bool s2 = (s_pos[j] >> 1) & 1;
-        const Cv sg = s_sig[r * 2 + 1];
+        for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
+        if (v + kTT < nrows) {
+            const Sv *src = row_src(v + kTT);
+#pragma unroll
+            for (int m = 0; m < P; ++m) xn[m] = src[m];
+        }
         Yv *Yr = Y + r * nin * PP + w * P;
-        if (bits & (1 << 4)) row_interp<P, 0, RHO1, C>(Lt, PH, x, s2, sg, Yr);
-        if (bits & (1 << 5)) row_interp<P, 1, RHO1, C>(Lt, PH, x, s2, sg, Yr + ysz);
+        if (bits & (1 << 4)) row_interp<P, 0, C>(Rt, x, Yr);
+        if (bits & (1 << 5)) row_interp<P, 1, C>(Rt, x, Yr + ysz);
     }
     __syncthreads();
 
@@ -380,6 +380,16 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
             const int a0 = s_out[r * 4 + (t2 << 1)], a1 = s_out[r * 4 + 1 + (t2 << 1)];
             const int c0 = s_cj[bl * 4 + 0], c2 = s_cj[bl * 4 + 2];
             const int c1 = s_cj[bl * 4 + 1], c3 = s_cj[bl * 4 + 3];
+            // weights of the children at column m: G(s2, t2, m), sigma of
+            // axis 2 with s2 = 1, sigma of axis 1 on the s1 = 1 sum
+            Cv g0 = gcoef<Cv>(Ct, 0, t2, m, P), g1 = gcoef<Cv>(Ct, 1, t2, m, P);
+            if (!RHO1) g1 = cmul(g1, s_sig[r * 2 + 1]);
+            Cv h0 = g0, h1 = g1;
+            if (!RHO1) {
+                const Cv sg = s_sig[r * 2];
+                h0 = cmul(h0, sg);
+                h1 = cmul(h1, sg);
+            }
             // one branch per child slot, not per element
             Cv z0[P], z1[P];
 #pragma unroll
@@ -387,43 +397,41 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
             if (c0 >= 0) {
                 const Yv *yp = Yr + c0 * PP + m;
 #pragma unroll
-                for (int l = 0; l < P; ++l) z0[l] = ld<Cv>(yp + l * P);
+                for (int l = 0; l < P; ++l) z0[l] = cmul(g0, ld<Cv>(yp + l * P));
             }
             if (c2 >= 0) {
                 const Yv *yp = Yr + c2 * PP + m;
 #pragma unroll
-                for (int l = 0; l < P; ++l) z0[l] = cadd(z0[l], ld<Cv>(yp + l * P));
+                for (int l = 0; l < P; ++l) cfma(z0[l], g1, ld<Cv>(yp + l * P));
             }
             if (c1 >= 0) {
                 const Yv *yp = Yr + c1 * PP + m;
 #pragma unroll
-                for (int l = 0; l < P; ++l) z1[l] = ld<Cv>(yp + l * P);
+                for (int l = 0; l < P; ++l) z1[l] = cmul(h0, ld<Cv>(yp + l * P));
             }
             if (c3 >= 0) {
                 const Yv *yp = Yr + c3 * PP + m;
 #pragma unroll
-                for (int l = 0; l < P; ++l) z1[l] = cadd(z1[l], ld<Cv>(yp + l * P));
+                for (int l = 0; l < P; ++l) cfma(z1[l], h1, ld<Cv>(yp + l * P));
             }
-            const bool h1 = (c1 >= 0) | (c3 >= 0);
-            if (!RHO1 && h1) {
-                const Cv sg = s_sig[r * 2];
-#pragma unroll
-                for (int l = 0; l < P; ++l) z1[l] = cmul(sg, z1[l]);
+            Sv *o0 = reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m;
+            Sv *o1 = reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m;
+            if (G == 1) {  // uniform: the whole line per thread, rows unrolled
+                if (a0 >= 0) line_interp<P, 0, C, Sv, true>(Rt, Ct, z0, z1, o0, P, 0, 1);
+                if (a1 >= 0) line_interp<P, 1, C, Sv, true>(Rt, Ct, z0, z1, o1, P, 0, 1);
+            } else {
+                if (a0 >= 0) line_interp<P, 0, C>(Rt, Ct, z0, z1, o0, P, grp, G);
+                if (a1 >= 0) line_interp<P, 1, C>(Rt, Ct, z0, z1, o1, P, grp, G);
             }
-            if (a0 >= 0)
-                col_interp_g<P, 0, S, C>(Lt, LP, PH, z0, z1, h1,
-                    reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m, grp, G);
-            if (a1 >= 0)
-                col_interp_g<P, 1, S, C>(Lt, LP, PH, z0, z1, h1,
-                    reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m, grp, G);
         }
     }
 }
 
 // One work item per work-group (single transform).
-// Waves per SIMD the register allocation must allow: five (at most 96
-// VGPRs) up to p = 9; the larger grids of p >= 10 need the full register file.
-template <int D, int P> constexpr int min_waves() { return (D == 2 && P <= 9) ? 5 : 1; }
+// Waves per SIMD the register allocation must allow: four (at most 128
+// VGPRs) up to p = 9 (five, at 96 VGPRs, spills in stage 2 and is slower);
+// the larger grids of p >= 10 need the full register file.
+template <int D, int P> constexpr int min_waves() { return (D == 2 && P <= 9) ? 4 : 1; }
 
 template <int P, bool RHO1, typename S, typename C>
 __global__ __launch_bounds__(kTT, (min_waves<2, P>())) void k_translate2d(TArgs a)
@@ -445,7 +453,7 @@ __global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
 // for every step, so late-starting work-groups cannot leave a tail; a
 // work-group finishes when the counter passes the end.
 template <int D, int P, typename S, typename C>
-__global__ __launch_bounds__(kTT, (min_waves<D, P>() > 1 ? 4 : 1)) void k_translate_batched(
+__global__ __launch_bounds__(kTT, (min_waves<D, P>())) void k_translate_batched(
     const TArgs *__restrict__ descs,
                                                              const int64_t *__restrict__ prefix,
                                                              int ndesc, int64_t total,
@@ -515,11 +523,7 @@ int translate_cap_blocks(int d, int p, int precision, int budget)
 {
     int PD = p;
     for (int a = 1; a < d; ++a) PD *= p;
-#ifdef BFSFT_MIXED_Y64
-    const int elem = precision != BFSFT_FP32 ? 16 : 8;
-#else
     const int elem = precision == BFSFT_FP64 ? 16 : 8;
-#endif
     int cap = budget / (PD * elem);
     const int one_box = d == 2 ? 2 * 4 : 8 + 2;  // a single box with all children
     if (cap < one_box) cap = one_box;
@@ -554,11 +558,7 @@ int translate_rows(int cap, int cost_max, int64_t nap, int kind)
 
 namespace {
 
-#ifdef BFSFT_MIXED_Y64
-size_t ysize(int precision) { return precision != BFSFT_FP32 ? 16 : 8; }
-#else
 size_t ysize(int precision) { return precision == BFSFT_FP64 ? 16 : 8; }
-#endif
 
 }  // namespace
 

@@ -26,14 +26,13 @@ struct TArgs {
     const uint64_t *x_keys;
     const int32_t *k_cb;
     const uint64_t *k_keys;
-    const int2 *tiles;
+    const int4 *tiles;
     int ntile;
     int rows;
     int64_t nap;
     const double2 *sig;
-    const void *Lt;  // [2][P][P] complex, compute precision
-    const void *PH;  // [2][P] complex, compute precision
-    const void *LP;  // [2][P][P] complex, compute precision: PH_t[l] L_t[l][l']
+    const void *R;   // [2][P][P] real, compute precision: R_t
+    const void *C;   // [2 s][2 t][P] complex, compute precision: G(s, t, l)
 };
 
 // Descriptor i of a device array, read through the constant address space:
@@ -57,9 +56,8 @@ __device__ __forceinline__ TArgs load_desc(const TArgs *descs, int i)
     a.rows = d->rows;
     a.nap = d->nap;
     a.sig = d->sig;
-    a.Lt = d->Lt;
-    a.PH = d->PH;
-    a.LP = d->LP;
+    a.R = d->R;
+    a.C = d->C;
     return a;
 }
 
@@ -80,14 +78,13 @@ inline TArgs make_targs(const Launch &c, const LevelArgs &la)
     a.rows = la.rows;
     a.sig = reinterpret_cast<const double2 *>(la.sig);
     const bool f32 = c.precision == BFSFT_FP32;
-    a.Lt = f32 ? (const void *)c.tb->L32 : (const void *)c.tb->L64;
-    a.PH = f32 ? (const void *)c.tb->PH32 : (const void *)c.tb->PH64;
-    a.LP = f32 ? (const void *)c.tb->LP32 : (const void *)c.tb->LP64;
+    a.R = f32 ? (const void *)c.tb->R32 : (const void *)c.tb->R64;
+    a.C = f32 ? (const void *)c.tb->C32 : (const void *)c.tb->C64;
     return a;
 }
 
-// Row structure of L_t: row l is the unit vector of node (t q + l) / 2 when
-// t q + l is even, a full interpolation row otherwise.
+// Row structure of R_t (and L_t): row l is the unit vector of node (t q + l) / 2
+// when t q + l is even, a full interpolation row otherwise.
 template <int P, int T> struct Rows {
     static constexpr int Q = P - 1;
     static constexpr __host__ __device__ bool copy(int l) { return ((T * Q + l) & 1) == 0; }
@@ -124,26 +121,34 @@ struct Item2D {
     int all;  // union of the rows' output bits
 };
 
-// Per-work-group tables of a 2D item, filled cooperatively:
-//   s_out[r][t]   output row a of child t of row a' (or -1),
-//   s_bits[r]     bit t: child t present; bit 4 + t2: a child with that t2,
-//   s_sig[r][ax]  exp(2 pi i rho i_{A'}) per axis (1 when rho = 1),
-//   s_pos[j]      child position s of input j of the tile,
-//   s_cj[b][s]    local input index of child s of box b (or -1).
-template <typename Cv>
-__device__ __forceinline__ Item2D setup2d(const TArgs &a, int64_t gid, int *s_out, int *s_bits,
-                                          Cv *s_sig, unsigned char *s_pos, signed char *s_cj)
+// Uniform description of work item gid (no memory but the tile record).
+__device__ __forceinline__ Item2D item2d(const TArgs &a, int64_t gid)
 {
     Item2D it;
     const int64_t g = gid / a.ntile;
     const int tile = (int)(gid - g * a.ntile);
     it.ap0 = g * a.rows;
     it.R = (int)min((int64_t)a.rows, a.nap - it.ap0);
-    const int2 bt = a.tiles[tile];
+    const int4 bt = a.tiles[tile];
     it.b0 = bt.x;
     it.nb = bt.y - bt.x;
-    it.J0 = a.k_cb[it.b0];
-    it.nin = a.k_cb[bt.y] - it.J0;
+    it.J0 = bt.z;
+    it.nin = bt.w - bt.z;
+    it.all = 0;
+    return it;
+}
+
+// Per-work-group tables of a 2D item, filled cooperatively (ends with a
+// barrier; sets it.all):
+//   s_out[r][t]   output row a of child t of row a' (or -1),
+//   s_bits[r]     bit t: child t present; bit 4 + t2: a child with that t2,
+//   s_sig[r][ax]  exp(2 pi i rho i_{A'}) per axis (1 when rho = 1),
+//   s_pos[j]      child position s of input j of the tile,
+//   s_cj[b][s]    local input index of child s of box b (or -1).
+template <typename Cv>
+__device__ __forceinline__ void tables2d(const TArgs &a, Item2D &it, int *s_out, int *s_bits, Cv *s_sig,
+                                         unsigned char *s_pos, signed char *s_cj)
+{
     for (int i = threadIdx.x; i < it.nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[it.J0 + i] & 3);
     for (int bl = threadIdx.x; bl < it.nb; bl += kTT) {
         signed char cj[4] = {-1, -1, -1, -1};
@@ -175,6 +180,14 @@ __device__ __forceinline__ Item2D setup2d(const TArgs &a, int64_t gid, int *s_ou
     int all = 0;
     for (int r = 0; r < it.R; ++r) all |= s_bits[r];
     it.all = all;
+}
+
+template <typename Cv>
+__device__ __forceinline__ Item2D setup2d(const TArgs &a, int64_t gid, int *s_out, int *s_bits,
+                                          Cv *s_sig, unsigned char *s_pos, signed char *s_cj)
+{
+    Item2D it = item2d(a, gid);
+    tables2d<Cv>(a, it, s_out, s_bits, s_sig, s_pos, s_cj);
     return it;
 }
 

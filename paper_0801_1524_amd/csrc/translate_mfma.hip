@@ -1,8 +1,10 @@
 // Step 3 of Section 2.2 in 2D on the FP64 matrix cores of gfx950.
 //
-// The translation of a level is the same as in translate.hip (per axis,
-// w^{AB}[l] = sum_s f(s, t, l) (L_t w^{A'B_s})[l]); only the dot rows of
-// L_t (floor(p/2) per t) are contractions, and those run as
+// The translation of a level is the same as in translate.hip: per axis,
+// w^{AB}[l] = sum_s f(s, t, l) (L_t w^{A'B_s})[l], here applied to the
+// rotated state w^ = E w, i.e. with the operator E L_t E^{-1} (E = diag of
+// exp(-i pi rho k / q)), whose copy rows carry the phase E[l] / E[node].
+// Only the dot rows (floor(p/2) per t) are contractions, and those run as
 // v_mfma_f64_16x16x4f64 products with the operator as the 16-row A
 // operand and 16 state lines as the B operand.  Complex products are
 // written in real form: a complex row (w_0 .. w_{p-1}) becomes the 2p reals
@@ -43,11 +45,12 @@ typedef double dx4 __attribute__((ext_vector_type(4)));
 // Shape of the per-lane operator tables of order p.
 struct MShape {
     int P, Q, ND, NC, KS1, NB, REM;
-    int oT1, oT2, oDPH, oNPH, size;
+    int oT1, oT2, oDPH, oNPH, oCF, size;
     __host__ __device__ constexpr explicit MShape(int p)
         : P(p), Q(p - 1), ND(p / 2), NC(p - p / 2), KS1((2 * p + 3) / 4), NB(p / 4), REM(p % 4),
           oT1(0), oT2(((2 * p + 3) / 4) * 64), oDPH(((2 * p + 3) / 4) * 64 + p * 64),
-          oNPH(((2 * p + 3) / 4) * 64 + p * 64 + 256), size(((2 * p + 3) / 4) * 64 + p * 64 + 256 + 2 * p)
+          oNPH(((2 * p + 3) / 4) * 64 + p * 64 + 256), oCF(((2 * p + 3) / 4) * 64 + p * 64 + 256 + 2 * p),
+          size(((2 * p + 3) / 4) * 64 + p * 64 + 256 + 6 * p)
     {
     }
 };
@@ -75,11 +78,17 @@ __device__ __forceinline__ double realform(int part, int kpart, double2 w)
 //                 im z0, re z1, im z1) of node 4b + kq; the p mod 4 last
 //                 steps give component kq of the remaining nodes,
 //   DPH[h][lane]: phase PH_t[row] of complex output 2 kq + h of stage 1,
-//   NPH[node]:    phase of the copy rows through node (same for t = 0, 1).
+//   NPH[node]:    phase of the copy rows through node (same for t = 0, 1),
+//   CF[t][node]:  entry E[l] / E[node] of the copy row l = 2 node - t q.
+// Operator entries are those of the rotated state, E[row] L_t[row][k] / E[k].
 __global__ void k_mfma_tables(int p, const double2 *__restrict__ L64, const double2 *__restrict__ PH64,
-                              double *__restrict__ mt)
+                              const double2 *__restrict__ erot, double *__restrict__ mt)
 {
     const MShape m(p);
+    auto lrot = [&](int t, int row, int k) {
+        const double2 ek = erot[k];
+        return cmul(cmul(erot[row], L64[(t * p + row) * p + k]), make_double2(ek.x, -ek.y));
+    };
     const int lane = threadIdx.x, i = lane & 15, kq = lane >> 4;
     const int co = 2 * (i & 3) + (i >> 3), part = (i >> 2) & 1;
     const bool orow = co < 2 * m.ND;
@@ -87,7 +96,7 @@ __global__ void k_mfma_tables(int p, const double2 *__restrict__ L64, const doub
     for (int s = 0; s < m.KS1; ++s) {
         const int k = 4 * s + kq;
         double v = 0.0;
-        if (orow && k < 2 * p) v = realform(part, k & 1, L64[(t * p + row) * p + (k >> 1)]);
+        if (orow && k < 2 * p) v = realform(part, k & 1, lrot(t, row, k >> 1));
         mt[m.oT1 + s * 64 + lane] = v;
     }
     for (int s = 0; s < p; ++s) {
@@ -101,7 +110,7 @@ __global__ void k_mfma_tables(int p, const double2 *__restrict__ L64, const doub
         }
         double v = 0.0;
         if (orow) {
-            double2 w = L64[(t * p + row) * p + node];
+            double2 w = lrot(t, row, node);
             if (comp >= 2) w = cmul(PH64[t * p + row], w);
             v = realform(part, comp & 1, w);
         }
@@ -120,6 +129,16 @@ __global__ void k_mfma_tables(int p, const double2 *__restrict__ L64, const doub
         mt[m.oNPH + 2 * nd] = ph.x;
         mt[m.oNPH + 2 * nd + 1] = ph.y;
     }
+    if (lane < 2 * p) {
+        const int t = lane / p, nd = lane % p, l = 2 * nd - t * m.Q;
+        double2 cf = make_double2(0.0, 0.0);
+        if (l >= 0 && l < p) {
+            const double2 en = erot[nd];
+            cf = cmul(erot[l], make_double2(en.x, -en.y));
+        }
+        mt[m.oCF + 2 * lane] = cf.x;
+        mt[m.oCF + 2 * lane + 1] = cf.y;
+    }
 }
 
 template <int P, bool RHO1, typename S>
@@ -136,9 +155,11 @@ __global__ __launch_bounds__(kTT) void k_translate2d_mfma(TArgs a, const double 
     __shared__ unsigned char s_pos[kInMax];
     __shared__ int s_cj4[kInMax];  // [b]: local child index of slots 0..3, one byte each
     __shared__ double2 s_nph[P];
+    __shared__ double2 s_cf[2 * P];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4, j16 = lane & 15;
     if (tid < P) s_nph[tid] = make_double2(mt[M.oNPH + 2 * tid], mt[M.oNPH + 2 * tid + 1]);
+    if (tid < 2 * P) s_cf[tid] = make_double2(mt[M.oCF + 2 * tid], mt[M.oCF + 2 * tid + 1]);
     const Item2D it = setup2d<double2>(a, blockIdx.x, s_out, s_bits, s_sig, s_pos,
                                        reinterpret_cast<signed char *>(s_cj4));
     const int R = it.R, nb = it.nb, nin = it.nin;
@@ -218,7 +239,7 @@ __global__ __launch_bounds__(kTT) void k_translate2d_mfma(TArgs a, const double 
                 if (!((bits >> (4 + t2)) & 1)) continue;
                 const int l2 = 2 * jc + (t2 & Q & 1);
                 const int node = (t2 * Q + l2) >> 1;
-                double2 v = ld<double2>(X + n * P + node);
+                double2 v = cmul(ld<double2>(X + n * P + node), s_cf[t2 * P + node]);
                 if (s2) v = cmul(v, RHO1 ? s_nph[node] : cmul(s_sig[r * 2 + 1], s_nph[node]));
                 if (!RHO1 && s1) v = cmul(v, s_sig[r * 2]);
                 st(Y + t2 * ysz + n * P + l2, v);
@@ -324,8 +345,8 @@ __global__ __launch_bounds__(kTT) void k_translate2d_mfma(TArgs a, const double 
                 // position t1 with t1 q + l1 = 2 node
                 auto copies = [&](int node, double2 z0, double2 z1) {
                     const double2 v = cadd(z0, cmul(s_nph[node], z1));
-                    if (o0 && 2 * node <= Q) st(o0 + (2 * node) * P, v);
-                    if (o1 && 2 * node >= Q) st(o1 + (2 * node - Q) * P, v);
+                    if (o0 && 2 * node <= Q) st(o0 + (2 * node) * P, cmul(v, s_cf[node]));
+                    if (o1 && 2 * node >= Q) st(o1 + (2 * node - Q) * P, cmul(v, s_cf[P + node]));
                 };
 #pragma unroll
                 for (int bk = 0; bk < NB; ++bk) copies(4 * bk + kq, z0o[bk], z1o[bk]);
@@ -361,7 +382,8 @@ size_t translate_mfma_table_doubles(int p) { return (size_t)MShape(p).size; }
 void build_mfma_tables(const Tables &tb, int p, double *dst, hipStream_t s)
 {
     k_mfma_tables<<<1, 64, 0, s>>>(p, reinterpret_cast<const double2 *>(tb.L64),
-                                   reinterpret_cast<const double2 *>(tb.PH64), dst);
+                                   reinterpret_cast<const double2 *>(tb.PH64),
+                                   reinterpret_cast<const double2 *>(tb.erot), dst);
     BF_HIP(hipGetLastError());
 }
 
