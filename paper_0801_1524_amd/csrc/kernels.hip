@@ -344,11 +344,7 @@ __device__ __forceinline__ void direct_item(const DirectDesc &dd, int64_t gid)
 #pragma unroll
         for (int l = 0; l < P; ++l) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const double2 v = cmul(c[g], e);
-                acc[g][l].x += v.x;
-                acc[g][l].y += v.y;
-            }
+            for (int g = 0; g < G; ++g) cfma(acc[g][l], c[g], e);
             e = cmul(e, rl);
         }
     }
