@@ -244,7 +244,7 @@ int kernel_choices(const bfsft_plan *P)
 void autotune_single(bfsft_plan *P)
 {
     const int choices = kernel_choices(P);
-    const std::string key = "single2/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
+    const std::string key = "single3/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
                             prec_name(P->precision) + "/L" + std::to_string(P->L) + "/k" +
                             std::to_string(choices);
     std::vector<int> v;
@@ -262,14 +262,15 @@ void autotune_single(bfsft_plan *P)
     const size_t bytes = state_bytes(P);
     BF_HIP(hipMemsetAsync(P->buf[0], 0, bytes, P->stream));
     BF_HIP(hipMemsetAsync(P->buf[1], 0, bytes, P->stream));
-    const int cand[] = {8, 12, 16, 24, 32, 40, 48, 60};
+    // budgets a few KB apart: the threads a tile fills depend on them finely
+    const int cand[] = {8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 54, 60};
     std::vector<double> best(P->L, 1e30);
     std::vector<int> pick(P->L, 32), pk(P->L, 0);
     for (int kind = 0; kind < 2; ++kind) {
         if (!(choices & (1 << kind))) continue;
         for (int kb : cand) {
             build_tiles_levels(P, std::vector<int>(P->L, kb * 1024), std::vector<int>(P->L, kind));
-            const std::vector<double> ms = time_levels(P, 2);
+            const std::vector<double> ms = time_levels(P, 3);
             for (int l = 0; l < P->L; ++l)
                 if (ms[l] < best[l]) {
                     best[l] = ms[l];
