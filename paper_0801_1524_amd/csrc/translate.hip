@@ -85,23 +85,16 @@ __device__ __forceinline__ void row_interp(cptr<C> Rt, const typename CV<C>::t *
 // One output line at position T along the contracted axis, written with
 // stride `stride` to a destination of element type Dv (LDS or HBM):
 //   o[l] = G(0, T, l) (R_T z0)[l] + G(1, T, l) (R_T z1)[l],
-// z1 carrying sigma already.  Only the output rows of group g of G are
-// written (dot rows k = g, g + G, ... and every G-th copy row; g is uniform
-// across the wave); G = 1 writes the whole line.
-template <int P, int T, typename C, typename Dv, bool ONE = false>
+// z1 carrying sigma already.
+template <int P, int T, typename C, typename Dv>
 __device__ __forceinline__ void line_interp(cptr<C> Rt, cptr<C> Ct, const typename CV<C>::t *z0,
-                                            const typename CV<C>::t *z1, Dv *dst, int stride, int g,
-                                            int G)
+                                            const typename CV<C>::t *z1, Dv *dst, int stride)
 {
     using Cv = typename CV<C>::t;
     using RW = Rows<P, T>;
     constexpr int PP = P * P, Q = P - 1;
-    if (ONE) {
-        g = 0;
-        G = 1;
-    }
 #pragma unroll
-    for (int k = g; k < RW::ndot; k += G) {
+    for (int k = 0; k < RW::ndot; ++k) {
         const int l = RW::first_dot + 2 * k;
         Cv a = czero<Cv>(), b = czero<Cv>();
 #pragma unroll
@@ -117,7 +110,6 @@ __device__ __forceinline__ void line_interp(cptr<C> Rt, cptr<C> Ct, const typena
 #pragma unroll
     for (int l = 0; l < P; ++l) {
         if (!RW::copy(l)) continue;
-        if (RW::copy_index(l) % G != g) continue;
         const int n = (T * Q + l) / 2;
         Cv o = cmul(gcoef<Cv>(Ct, 0, T, l, P), z0[n]);
         cfma(o, gcoef<Cv>(Ct, 1, T, l, P), z1[n]);
@@ -253,9 +245,9 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                     }
                     Yv *dst = Y2r + (bl * 2 + e0) * P3 + l * P2 + n;
                     if (t1 == 0)
-                        line_interp<P, 0, C, Yv, true>(Rt, Ct, z0, z1, dst, P, 0, 1);
+                        line_interp<P, 0, C>(Rt, Ct, z0, z1, dst, P);
                     else
-                        line_interp<P, 1, C, Yv, true>(Rt, Ct, z0, z1, dst, P, 0, 1);
+                        line_interp<P, 1, C>(Rt, Ct, z0, z1, dst, P);
                 }
             }
             __syncthreads();
@@ -283,11 +275,11 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                         if (!RHO1) z1[l] = cmul(z1[l], sg0);
                     }
                     if (a0 >= 0)
-                        line_interp<P, 0, C, Sv, true>(Rt, Ct, z0, z1,
-                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2, 0, 1);
+                        line_interp<P, 0, C>(Rt, Ct, z0, z1,
+                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2);
                     if (a1 >= 0)
-                        line_interp<P, 1, C, Sv, true>(Rt, Ct, z0, z1,
-                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2, 0, 1);
+                        line_interp<P, 1, C>(Rt, Ct, z0, z1,
+                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2);
                 }
             }
             __syncthreads();
@@ -358,19 +350,22 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     }
     __syncthreads();
 
-    // stage 2: every output column once per t2, both output positions t1,
-    // all rows side by side.  Narrow work splits the output rows over G
-    // wave-aligned groups of threads, so all four waves work.
+    // stage 2: one work unit per (t2, output column), over the positions t2
+    // some row needs, each with both output positions t1 and the whole
+    // column.  (Splitting a column's rows over several threads, to keep all
+    // waves busy when units are few, repeats the children's sums and is
+    // slower: idle waves cost no issue slots.)
     const int ncol = nb * P;
     const float inv_ncol = 1.0f / (float)ncol;
     const int ntot = R * ncol;
-    const int G = (ntot <= 64 && kWaves >= 4) ? 4 : ((ntot <= 128 && kWaves >= 2) ? 2 : 1);
-    const int span = kTT / G;
-    const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / span);
-    const int lane = (int)threadIdx.x - grp * span;
-    for (int t2 = 0; t2 < 2; ++t2) {
-        if (!(all & (1 << (4 + t2)))) continue;  // uniform
-        for (int v = lane; v < ntot; v += span) {
+    const int need = (all >> 4) & 3;  // t2 = 0, 1 needed by some row (uniform)
+    const int units = ((need & 1) + (need >> 1)) * ntot;
+    const int tfirst = (need & 1) ? 0 : 1;
+    {
+        for (int u = threadIdx.x; u < units; u += kTT) {
+            const bool second = u >= ntot;  // only when both positions are needed
+            const int t2 = second ? 1 : tfirst;
+            const int v = second ? u - ntot : u;
             const int r = (int)(((float)v + 0.5f) * inv_ncol);
             const int col = v - r * ncol;
             const int bits = s_bits[r];
@@ -416,13 +411,8 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
             }
             Sv *o0 = reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m;
             Sv *o1 = reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m;
-            if (G == 1) {  // uniform: the whole line per thread, rows unrolled
-                if (a0 >= 0) line_interp<P, 0, C, Sv, true>(Rt, Ct, z0, z1, o0, P, 0, 1);
-                if (a1 >= 0) line_interp<P, 1, C, Sv, true>(Rt, Ct, z0, z1, o1, P, 0, 1);
-            } else {
-                if (a0 >= 0) line_interp<P, 0, C>(Rt, Ct, z0, z1, o0, P, grp, G);
-                if (a1 >= 0) line_interp<P, 1, C>(Rt, Ct, z0, z1, o1, P, grp, G);
-            }
+            if (a0 >= 0) line_interp<P, 0, C>(Rt, Ct, z0, z1, o0, P);
+            if (a1 >= 0) line_interp<P, 1, C>(Rt, Ct, z0, z1, o1, P);
         }
     }
 }
