@@ -92,9 +92,9 @@ LevelArgs level_args(const bfsft_plan *P, int l, const void *in, void *out)
     a.in_row = P->tk.count[l + 1];
     a.out_row = P->tk.count[l];
     a.x_cb = P->tx.child_beg[L - l - 1];
-    a.x_keys = P->tx.keys[L - l];
     a.k_cb = P->tk.child_beg[l];
-    a.k_keys = P->tk.keys[l + 1];
+    a.x_slot = P->tx.slots[L - l - 1];
+    a.k_slot = P->tk.slots[l];
     a.tiles = P->tiles[l];
     a.ntile = P->ntile[l];
     a.cost_max = P->cost_max[l];

@@ -48,6 +48,8 @@ struct Tree {
     std::vector<int64_t> count;        // [L+1] boxes per level
     std::vector<uint64_t *> keys;      // [L+1] device, Morton keys of level m
     std::vector<int32_t *> child_beg;  // [L] device, level m: [count[m]+1] first child in level m+1
+    std::vector<uint64_t *> slots;     // [L] device, level m: [count[m]] byte s = child at position s,
+                                       //   as an offset from child_beg (0xff: no such child)
     std::vector<std::vector<int32_t>> child_beg_host;  // same, host copies (tiling)
     int32_t *perm = nullptr;           // device [npts]: Morton-sorted position -> original index
     int32_t *leaf_beg = nullptr;       // device [count[L]+1]: sorted points of each leaf
@@ -92,9 +94,9 @@ struct LevelArgs {
     int64_t in_row;          // boxes per input row  = count_K[l+1]
     int64_t out_row;         // boxes per output row = count_K[l]
     const int32_t *x_cb;     // T_X level L-l-1: children range in level L-l, [nap+1]
-    const uint64_t *x_keys;  // T_X level L-l keys (child position t)
     const int32_t *k_cb;     // T_K level l: children range in level l+1
-    const uint64_t *k_keys;  // T_K level l+1 keys (child position s)
+    const uint64_t *x_slot;  // T_X level L-l-1: child-position slots (Tree::slots)
+    const uint64_t *k_slot;  // T_K level l: child-position slots
     const int4 *tiles;       // [ntile] (b0, b1, first child, end of children)
     int ntile;
     int cost_max;            // most LDS blocks any tile needs (translate_tile_cost)

@@ -23,9 +23,9 @@ struct TArgs {
     void *out;
     int64_t in_row, out_row;
     const int32_t *x_cb;
-    const uint64_t *x_keys;
     const int32_t *k_cb;
-    const uint64_t *k_keys;
+    const uint64_t *x_slot;
+    const uint64_t *k_slot;
     const int4 *tiles;
     int ntile;
     int rows;
@@ -48,9 +48,9 @@ __device__ __forceinline__ TArgs load_desc(const TArgs *descs, int i)
     a.in_row = d->in_row;
     a.out_row = d->out_row;
     a.x_cb = d->x_cb;
-    a.x_keys = d->x_keys;
     a.k_cb = d->k_cb;
-    a.k_keys = d->k_keys;
+    a.x_slot = d->x_slot;
+    a.k_slot = d->k_slot;
     a.tiles = d->tiles;
     a.ntile = d->ntile;
     a.rows = d->rows;
@@ -69,9 +69,9 @@ inline TArgs make_targs(const Launch &c, const LevelArgs &la)
     a.in_row = la.in_row;
     a.out_row = la.out_row;
     a.x_cb = la.x_cb;
-    a.x_keys = la.x_keys;
     a.k_cb = la.k_cb;
-    a.k_keys = la.k_keys;
+    a.x_slot = la.x_slot;
+    a.k_slot = la.k_slot;
     a.tiles = la.tiles;
     a.ntile = la.ntile;
     a.nap = la.nap;
@@ -149,26 +149,29 @@ template <typename Cv>
 __device__ __forceinline__ void tables2d(const TArgs &a, Item2D &it, int *s_out, int *s_bits, Cv *s_sig,
                                          unsigned char *s_pos, signed char *s_cj)
 {
-    for (int i = threadIdx.x; i < it.nin; i += kTT) s_pos[i] = (unsigned char)(a.k_keys[it.J0 + i] & 3);
+    // from the child-position slot words: one load per box and per row
     for (int bl = threadIdx.x; bl < it.nb; bl += kTT) {
-        signed char cj[4] = {-1, -1, -1, -1};
-        for (int j = a.k_cb[it.b0 + bl]; j < a.k_cb[it.b0 + bl + 1]; ++j)
-            cj[a.k_keys[j] & 3] = (signed char)(j - it.J0);
+        const int kcb = a.k_cb[it.b0 + bl];
+        const uint64_t w = a.k_slot[it.b0 + bl];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) s_cj[bl * 4 + s] = cj[s];
+        for (int s = 0; s < 4; ++s) {
+            const int o = (int)((w >> (8 * s)) & 0xffu);
+            s_cj[bl * 4 + s] = o == 0xff ? (signed char)-1 : (signed char)(kcb + o - it.J0);
+            if (o != 0xff) s_pos[kcb + o - it.J0] = (unsigned char)s;
+        }
     }
     if ((int)threadIdx.x < it.R) {
         const int r = threadIdx.x;
         const int64_t ap = it.ap0 + r;
+        const int xcb = a.x_cb[ap];
+        const uint64_t w = a.x_slot[ap];
         int bits = 0;
-        int o[4] = {-1, -1, -1, -1};
-        for (int i = a.x_cb[ap]; i < a.x_cb[ap + 1]; ++i) {
-            const int t = (int)(a.x_keys[i] & 3);
-            o[t] = i;
-            bits |= (1 << t) | (1 << (4 + (t >> 1)));
-        }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) s_out[r * 4 + t] = o[t];
+        for (int t = 0; t < 4; ++t) {
+            const int o = (int)((w >> (8 * t)) & 0xffu);
+            s_out[r * 4 + t] = o == 0xff ? -1 : xcb + o;
+            if (o != 0xff) bits |= (1 << t) | (1 << (4 + (t >> 1)));
+        }
         s_bits[r] = bits;
         Cv one;
         one.x = 1;

@@ -221,6 +221,24 @@ __global__ void k_leaf_of(const int32_t *__restrict__ perm, const uint32_t *__re
 
 __global__ void k_store_i32(int32_t *p, int32_t v) { *p = v; }
 
+// child-position slots of every box of a level: byte s of slots[b] is the
+// offset (from child_beg[b]) of the child at position s, 0xff if absent
+__global__ void k_slots(const uint64_t *__restrict__ child_keys, const int32_t *__restrict__ child_beg, int n,
+                        int d, uint64_t *__restrict__ slots)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const uint64_t pm = (1ull << d) - 1ull;
+    uint64_t w = ~0ull;
+    const int j0 = child_beg[b];
+    for (int j = j0; j < child_beg[b + 1]; ++j) {
+        const int s = (int)(child_keys[j] & pm);
+        w &= ~(0xffull << (8 * s));
+        w |= (uint64_t)(j - j0) << (8 * s);
+    }
+    slots[b] = w;
+}
+
 inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 uint32_t read_count(const uint32_t *flags, const uint32_t *pos, int n, hipStream_t s)
@@ -295,6 +313,7 @@ void build_tree(Tree &t, const double *pts, int64_t n64, int d, int L, int64_t N
     t.count.assign(L + 1, 0);
     t.keys.assign(L + 1, nullptr);
     t.child_beg.assign(L, nullptr);
+    t.slots.assign(L, nullptr);
     t.child_beg_host.assign(L, {});
     if (n64 == 0) return;
     const int n = (int)n64;
@@ -357,6 +376,8 @@ void build_tree(Tree &t, const double *pts, int64_t n64, int d, int L, int64_t N
         k_compact<<<nblk(nc, 256), 256, 0, s>>>(t.keys[m + 1], nc, d, flags, pos, t.keys[m],
                                                t.child_beg[m]);
         k_store_i32<<<1, 1, 0, s>>>(t.child_beg[m] + np, nc);
+        t.slots[m] = (uint64_t *)arena.alloc(sizeof(uint64_t) * np);
+        k_slots<<<nblk(np, 256), 256, 0, s>>>(t.keys[m + 1], t.child_beg[m], np, d, t.slots[m]);
         BF_HIP(hipGetLastError());
     }
     for (int m = 0; m < L; ++m) {
