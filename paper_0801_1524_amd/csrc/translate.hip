@@ -311,23 +311,22 @@ struct Slots2D {
     uint64_t kslot = ~0ull, xslot = ~0ull;
 };
 
+// The loads are unconditional (indices clamped into range): a load under a
+// branch makes the compiler wait for it where the branch joins.
 __device__ __forceinline__ Slots2D load_slots(const TArgs &a, const Item2D &it)
 {
     Slots2D h;
     const int tid = threadIdx.x;
-    if (tid < it.nb) {
-        h.kcb = a.k_cb[it.b0 + tid];
-        h.kslot = a.k_slot[it.b0 + tid];
-    }
-    if (tid < it.R) {
-        h.xcb = a.x_cb[it.ap0 + tid];
-        h.xslot = a.x_slot[it.ap0 + tid];
-    }
+    const int bl = min(tid, it.nb - 1), r = min(tid, it.R - 1);
+    h.kcb = a.k_cb[it.b0 + bl];
+    h.kslot = a.k_slot[it.b0 + bl];
+    h.xcb = a.x_cb[it.ap0 + r];
+    h.xslot = a.x_slot[it.ap0 + r];
     return h;
 }
 
 // Fill the tables from the slot words (ends with a barrier; sets it.all).
-template <typename Cv>
+template <bool RHO1, typename Cv>
 __device__ __forceinline__ void fill_tables(const TArgs &a, Item2D &it, const Slots2D &h, Tables2D<Cv> &tb)
 {
     const int tid = threadIdx.x;
@@ -351,8 +350,8 @@ __device__ __forceinline__ void fill_tables(const TArgs &a, Item2D &it, const Sl
         one.x = 1;
         one.y = 0;
         const int64_t ap = it.ap0 + tid;
-        tb.sig[tid * 2] = a.sig ? cvt<Cv>(a.sig[ap * 2]) : one;
-        tb.sig[tid * 2 + 1] = a.sig ? cvt<Cv>(a.sig[ap * 2 + 1]) : one;
+        tb.sig[tid * 2] = (!RHO1 && a.sig) ? cvt<Cv>(a.sig[ap * 2]) : one;
+        tb.sig[tid * 2 + 1] = (!RHO1 && a.sig) ? cvt<Cv>(a.sig[ap * 2 + 1]) : one;
     }
     __syncthreads();
     int all = 0;
@@ -371,14 +370,13 @@ __device__ __forceinline__ const Sv *row_src(const TArgs &a, const Item2D &it, i
     return reinterpret_cast<const Sv *>(a.in) + ((it.ap0 + r) * a.in_row + it.J0) * PP + (v - r * rowlen) * P;
 }
 
+// row v, clamped to the last row (an unconditional load, see load_slots)
 template <int P, typename Sv>
 __device__ __forceinline__ void load_row(const TArgs &a, const Item2D &it, int v, Sv *xn)
 {
-    if (v < it.R * it.nin * P) {
-        const Sv *src = row_src<P, Sv>(a, it, v);
+    const Sv *src = row_src<P, Sv>(a, it, min(v, it.R * it.nin * P - 1));
 #pragma unroll
-        for (int m = 0; m < P; ++m) xn[m] = src[m];
-    }
+    for (int m = 0; m < P; ++m) xn[m] = src[m];
 }
 
 // Stage 1: every input row once, both output positions t2 it is needed
@@ -489,7 +487,7 @@ __device__ __forceinline__ void stage2_2d(const TArgs &a, const Item2D &it, cons
 }
 
 // One 2D work item: its tables from the slot words (independent loads),
-// the thread's first input row loaded before them, stage 1, stage 2.
+// the thread's first input row loaded alongside, stage 1, stage 2.
 template <int P, bool RHO1, typename S, typename C>
 __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, unsigned char *smem)
 {
@@ -499,9 +497,13 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     __shared__ Tables2D<Cv> tb;
     Yv *Y = reinterpret_cast<Yv *>(smem);  // [2 t2][R][nin][P][P]
     Item2D it = item2d(a, gid);
+    // slot words first (the tables need them first), then the first input
+    // row, which stays in flight through the table fill and its barrier
+    const Slots2D h = load_slots(a, it);
+    __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the row's
     Sv xn[P];
     load_row<P>(a, it, threadIdx.x, xn);
-    fill_tables(a, it, load_slots(a, it), tb);
+    fill_tables<RHO1>(a, it, h, tb);
     stage1_2d<P, S, C>(a, it, xn, Y, tb.bits);
     __syncthreads();
     stage2_2d<P, RHO1, S, C>(a, it, Y, tb);
