@@ -301,9 +301,14 @@ __device__ __forceinline__ void direct_item(const DirectDesc &dd, int64_t gid)
     const int s0 = dd.s0, L = dd.L;
     const int64_t N = dd.N, nB = dd.nB;
     if (gid >= dd.nA * nB * GL) return;
-    const int64_t ab = gid / GL;
-    const int grp = (int)(gid - ab * GL);
-    const int64_t a = ab / nB, b = ab - a * nB;
+    // B-major: the threads of a wave mostly share the box B, hence the
+    // source loop's trip count and the addresses of its loads
+    const int64_t per_b = dd.nA * GL;
+    const int64_t b = gid / per_b;
+    const int64_t rem = gid - b * per_b;
+    const int64_t a = rem / GL;
+    const int grp = (int)(rem - a * GL);
+    const int64_t ab = a * nB + b;
     int64_t iA[3] = {0, 0, 0};
     {
         const uint64_t key = dd.xkeys[a];
