@@ -159,25 +159,48 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     Yv *Y1 = reinterpret_cast<Yv *>(smem);  // [R][nin][P3]
     Yv *Y2 = Y1 + R * nin * P3;             // [R][nb][2][P3]
 
-    // tables from the child-position slot words (one load per box and row)
-    for (int bl = threadIdx.x; bl < nb; bl += kTT) {
-        const int kcb = a.k_cb[b0 + bl];
-        const uint64_t w = a.k_slot[b0 + bl];
+    // stage-1 rows (r, j, l, m) of the item, flattened; a thread's rows are
+    // v = tid, tid + kTT, ...; loads are unconditional (clamped to the last
+    // row), so the compiler does not wait for them where a branch joins
+    const int rowlen = nin * P2;
+    const int nrows = R * rowlen;
+    const float inv_rowlen = 1.0f / (float)rowlen;
+    const Sv *in0 = reinterpret_cast<const Sv *>(a.in) + (ap0 * a.in_row + J0) * P3;
+    const int64_t in_rs = a.in_row * P3;
+    auto load_row3 = [&](int v, Sv *xn) {
+        v = min(v, nrows - 1);
+        const int r = (int)(((float)v + 0.5f) * inv_rowlen);
+        const Sv *src = in0 + r * in_rs + (v - r * rowlen) * P;
+#pragma unroll
+        for (int m = 0; m < P; ++m) xn[m] = src[m];
+    };
+
+    // tables from the child-position slot words: one load per box and row,
+    // issued ahead of the first input row, which stays in flight through
+    // the table fill and its barrier
+    const int tid = threadIdx.x;
+    const int bl_ = min(tid, nb - 1), r_ = min(tid, R - 1);
+    const int kcb = a.k_cb[b0 + bl_];
+    const uint64_t kw = a.k_slot[b0 + bl_];
+    const int xcb = a.x_cb[ap0 + r_];
+    const uint64_t xw = a.x_slot[ap0 + r_];
+    __builtin_amdgcn_sched_barrier(0);
+    Sv xn[P];
+    load_row3(tid, xn);
+    for (int bl = tid; bl < nb; bl += kTT) {  // nb <= kInMax < kTT: one pass
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const int o = (int)((w >> (8 * s)) & 0xffu);
+            const int o = (int)((kw >> (8 * s)) & 0xffu);
             s_cj[bl * 8 + s] = o == 0xff ? (signed char)-1 : (signed char)(kcb + o - J0);
         }
     }
-    if (threadIdx.x < R) {
-        const int r = threadIdx.x;
+    if (tid < R) {
+        const int r = tid;
         const int64_t ap = ap0 + r;
-        const int xcb = a.x_cb[ap];
-        const uint64_t w = a.x_slot[ap];
         int bits = 0;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const int o = (int)((w >> (8 * t)) & 0xffu);
+            const int o = (int)((xw >> (8 * t)) & 0xffu);
             s_out[r * 8 + t] = o == 0xff ? -1 : xcb + o;
             if (o != 0xff) bits |= (1 << t) | (1 << (8 + (t >> 2))) | (1 << (16 + 2 * (t >> 2) + ((t >> 1) & 1)));
         }
@@ -186,7 +209,7 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
         one.x = 1;
         one.y = 0;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) s_sig[r * 3 + ax] = a.sig ? cvt<Cv>(a.sig[ap * 3 + ax]) : one;
+        for (int ax = 0; ax < 3; ++ax) s_sig[r * 3 + ax] = (!RHO1 && a.sig) ? cvt<Cv>(a.sig[ap * 3 + ax]) : one;
     }
     __syncthreads();
     int all = 0;
@@ -194,107 +217,113 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
 
     const cptr<C> Rt = (cptr<C>)(a.R);
     const cptr<C> Ct = (cptr<C>)(a.C);
+    bool first = true;  // xn holds the thread's first row
     for (int t2 = 0; t2 < 2; ++t2) {
-        if (!(all & (1 << (8 + t2)))) continue;
-        // stage 1
-        for (int r = 0; r < R; ++r) {
-            if (!(s_bits[r] & (1 << (8 + t2)))) continue;
-            const Sv *in = reinterpret_cast<const Sv *>(a.in) + ((ap0 + r) * a.in_row + J0) * P3;
-            Yv *Yr = Y1 + r * nin * P3;
-            for (int v = threadIdx.x; v < nin * P2; v += kTT) {
-                const Sv *src = in + v * P;
-                Cv x[P];
+        if (!(all & (1 << (8 + t2)))) continue;  // uniform
+        // stage 1: rows of the rows a' that need t2
+        if (!first) load_row3(tid, xn);
+        first = false;
+        for (int v = tid; v < nrows; v += kTT) {
+            const int r = (int)(((float)v + 0.5f) * inv_rowlen);
+            const int w = v - r * rowlen;
+            const bool need = (s_bits[r] >> (8 + t2)) & 1;
+            Cv x[P];
 #pragma unroll
-                for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(src[m]);
-                if (t2 == 0)
-                    row_interp<P, 0, C>(Rt, x, Yr + v * P);
-                else
-                    row_interp<P, 1, C>(Rt, x, Yr + v * P);
-            }
+            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
+            load_row3(v + kTT, xn);
+            if (!need) continue;
+            Yv *dst = Y1 + r * rowlen * P + w * P;
+            if (t2 == 0)
+                row_interp<P, 0, C>(Rt, x, dst);
+            else
+                row_interp<P, 1, C>(Rt, x, dst);
         }
         __syncthreads();
         for (int t1 = 0; t1 < 2; ++t1) {
             if (!(all & (1 << (16 + 2 * t2 + t1)))) continue;
-            // stage 2: lines along m, for (b, e0, l, n)
-            for (int r = 0; r < R; ++r) {
+            // stage 2: lines along m, for (r, b, e0, l, n)
+            const int len2 = nb * 2 * P2;
+            const float inv_len2 = 1.0f / (float)len2;
+            for (int v = tid; v < R * len2; v += kTT) {
+                const int r = (int)(((float)v + 0.5f) * inv_len2);
                 if (!(s_bits[r] & (1 << (16 + 2 * t2 + t1)))) continue;
+                const int vr = v - r * len2;
                 const Yv *Yr = Y1 + r * nin * P3;
                 Yv *Y2r = Y2 + r * nb * 2 * P3;
                 const Cv sg1 = s_sig[r * 3 + 1], sg2 = s_sig[r * 3 + 2];
-                for (int v = threadIdx.x; v < nb * 2 * P2; v += kTT) {
-                    const int bl = v / (2 * P2);
-                    const int rem = v - bl * 2 * P2;
-                    const int e0 = rem / P2;
-                    const int ln = rem - e0 * P2;
-                    const int l = ln / P, n = ln - l * P;
-                    const Cv g0 = gcoef<Cv>(Ct, 0, t2, n, P);
-                    Cv g1 = gcoef<Cv>(Ct, 1, t2, n, P);
-                    if (!RHO1) g1 = cmul(g1, sg2);
-                    Cv z0[P], z1[P];
+                const int bl = vr / (2 * P2);
+                const int rem = vr - bl * 2 * P2;
+                const int e0 = rem / P2;
+                const int ln = rem - e0 * P2;
+                const int l = ln / P, n = ln - l * P;
+                const Cv g0 = gcoef<Cv>(Ct, 0, t2, n, P);
+                Cv g1 = gcoef<Cv>(Ct, 1, t2, n, P);
+                if (!RHO1) g1 = cmul(g1, sg2);
+                Cv z0[P], z1[P];
 #pragma unroll
-                    for (int m = 0; m < P; ++m) z0[m] = z1[m] = czero<Cv>();
+                for (int m = 0; m < P; ++m) z0[m] = z1[m] = czero<Cv>();
 #pragma unroll
-                    for (int e12 = 0; e12 < 4; ++e12) {  // e1 = bit 0 of e12, e2 = bit 1
-                        const int c = s_cj[bl * 8 + e0 + 2 * e12];
-                        if (c < 0) continue;
-                        const Cv gw = (e12 & 2) ? g1 : g0;
-                        const Yv *yp = Yr + c * P3 + l * P2 + n;
-                        if (e12 & 1) {
+                for (int e12 = 0; e12 < 4; ++e12) {  // e1 = bit 0 of e12, e2 = bit 1
+                    const int c = s_cj[bl * 8 + e0 + 2 * e12];
+                    if (c < 0) continue;
+                    const Cv gw = (e12 & 2) ? g1 : g0;
+                    const Yv *yp = Yr + c * P3 + l * P2 + n;
+                    if (e12 & 1) {
 #pragma unroll
-                            for (int m = 0; m < P; ++m) cfma(z1[m], gw, ld<Cv>(yp + m * P));
-                        } else {
+                        for (int m = 0; m < P; ++m) cfma(z1[m], gw, ld<Cv>(yp + m * P));
+                    } else {
 #pragma unroll
-                            for (int m = 0; m < P; ++m) cfma(z0[m], gw, ld<Cv>(yp + m * P));
-                        }
+                        for (int m = 0; m < P; ++m) cfma(z0[m], gw, ld<Cv>(yp + m * P));
                     }
-                    if (!RHO1) {
-#pragma unroll
-                        for (int m = 0; m < P; ++m) z1[m] = cmul(z1[m], sg1);
-                    }
-                    Yv *dst = Y2r + (bl * 2 + e0) * P3 + l * P2 + n;
-                    if (t1 == 0)
-                        line_interp<P, 0, C>(Rt, Ct, z0, z1, dst, P);
-                    else
-                        line_interp<P, 1, C>(Rt, Ct, z0, z1, dst, P);
                 }
+                if (!RHO1) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) z1[m] = cmul(z1[m], sg1);
+                }
+                Yv *dst = Y2r + (bl * 2 + e0) * P3 + l * P2 + n;
+                if (t1 == 0)
+                    line_interp<P, 0, C>(Rt, Ct, z0, z1, dst, P);
+                else
+                    line_interp<P, 1, C>(Rt, Ct, z0, z1, dst, P);
             }
             __syncthreads();
-            // stage 3: lines along l, for (b, m, n); both output positions t0
-            for (int r = 0; r < R; ++r) {
+            // stage 3: lines along l, for (r, b, m, n); both output positions t0
+            const int len3 = nb * P2;
+            const float inv_len3 = 1.0f / (float)len3;
+            for (int v = tid; v < R * len3; v += kTT) {
+                const int r = (int)(((float)v + 0.5f) * inv_len3);
                 const int bits = s_bits[r];
                 if (!(bits & (1 << (16 + 2 * t2 + t1)))) continue;
+                const int vr = v - r * len3;
                 const Yv *Y2r = Y2 + r * nb * 2 * P3;
                 const Cv sg0 = s_sig[r * 3 + 0];
                 const int ta = 4 * t2 + 2 * t1;
                 const int a0 = s_out[r * 8 + ta], a1 = s_out[r * 8 + ta + 1];
-                for (int v = threadIdx.x; v < nb * P2; v += kTT) {
-                    const int bl = v / P2, mn = v - bl * P2;
-                    Cv z0[P], z1[P];
-                    const Yv *y0 = Y2r + (bl * 2 + 0) * P3 + mn;
-                    const Yv *y1 = Y2r + (bl * 2 + 1) * P3 + mn;
-                    const bool h1 = (s_cj[bl * 8 + 1] >= 0) | (s_cj[bl * 8 + 3] >= 0) |
-                                    (s_cj[bl * 8 + 5] >= 0) | (s_cj[bl * 8 + 7] >= 0);
-                    const bool h0 = (s_cj[bl * 8 + 0] >= 0) | (s_cj[bl * 8 + 2] >= 0) |
-                                    (s_cj[bl * 8 + 4] >= 0) | (s_cj[bl * 8 + 6] >= 0);
+                const int bl = vr / P2, mn = vr - bl * P2;
+                Cv z0[P], z1[P];
+                const Yv *y0 = Y2r + (bl * 2 + 0) * P3 + mn;
+                const Yv *y1 = Y2r + (bl * 2 + 1) * P3 + mn;
+                const bool h1 = (s_cj[bl * 8 + 1] >= 0) | (s_cj[bl * 8 + 3] >= 0) |
+                                (s_cj[bl * 8 + 5] >= 0) | (s_cj[bl * 8 + 7] >= 0);
+                const bool h0 = (s_cj[bl * 8 + 0] >= 0) | (s_cj[bl * 8 + 2] >= 0) |
+                                (s_cj[bl * 8 + 4] >= 0) | (s_cj[bl * 8 + 6] >= 0);
 #pragma unroll
-                    for (int l = 0; l < P; ++l) {
-                        z0[l] = h0 ? ld<Cv>(y0 + l * P2) : czero<Cv>();
-                        z1[l] = h1 ? ld<Cv>(y1 + l * P2) : czero<Cv>();
-                        if (!RHO1) z1[l] = cmul(z1[l], sg0);
-                    }
-                    if (a0 >= 0)
-                        line_interp<P, 0, C>(Rt, Ct, z0, z1,
-                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2);
-                    if (a1 >= 0)
-                        line_interp<P, 1, C>(Rt, Ct, z0, z1,
-                            reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2);
+                for (int l = 0; l < P; ++l) {
+                    z0[l] = h0 ? ld<Cv>(y0 + l * P2) : czero<Cv>();
+                    z1[l] = h1 ? ld<Cv>(y1 + l * P2) : czero<Cv>();
+                    if (!RHO1) z1[l] = cmul(z1[l], sg0);
                 }
+                if (a0 >= 0)
+                    line_interp<P, 0, C>(Rt, Ct, z0, z1,
+                        reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * P3 + mn, P2);
+                if (a1 >= 0)
+                    line_interp<P, 1, C>(Rt, Ct, z0, z1,
+                        reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * P3 + mn, P2);
             }
             __syncthreads();
         }
     }
 }
-
 
 // Per-work-group tables of a 2D item (static LDS).
 template <typename Cv> struct Tables2D {
