@@ -29,13 +29,15 @@
 // Work decomposition.  A work-group takes R consecutive rows a' of T_X level
 // L-l-1 and one tile of boxes b of T_K level l; the children of the tile are
 // a contiguous range of every input row (Morton order), and the outputs are
-// the rows a = children of each a'.  Per output position t2 along axis 2:
-//   stage 1: one thread per input row (a', j, l): Y = R_t2 along axis 2,
-//   stage 2: one thread per output column (a', b, m): sum the children with
-//            the same s1, each times its G(s2, t2, m), apply R_t1 along
-//            axis 1, combine the two sums with G(s1, t1, .) and write.
+// the rows a = children of each a'.
+//   stage 1: one thread per input row (a', j, l): Y = R_t2 along axis 2 for
+//            each output position t2 the row a' needs,
+//   stage 2: one thread per (t2, a', b, m): sum the children with the same
+//            s1, each times its G(s2, t2, m), apply R_t1 along axis 1 for
+//            t1 = 0 and 1, combine the two sums with G(s1, t1, .), write.
 // The operators of each stage depend only on t, so they are uniform across
-// the work-group and read through scalar loads.
+// the work-group and read through scalar loads.  The per-item tables come
+// from the trees' child-position slot words, one load per box and row.
 #include "bfsft_impl.h"
 #include "cplx.h"
 #include "dispatch.h"
