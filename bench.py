@@ -221,6 +221,24 @@ def time_precision(bf, torch, P, precision, steps, warmup):
     return {"ms_per_step": ms, "timing": tm, "info": info, "u": out}
 
 
+def copy_rate(torch):
+    """GB/s (bytes read + written) of a plain 1 GiB device-to-device copy on
+    the same GPU, timed over 5 copies after one untimed: the practical
+    streaming bandwidth, beside the 8 TB/s peak.  Outside the timed region."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    return round(rate, 1)
+
+
 def roofline(res, precision):
     info, tm = res["info"], res["timing"]
     nlev = info["levels"] - info["start_level"]                   # translation launches per execute
@@ -323,6 +341,8 @@ def main():
     head = min(passing, key=lambda k: results[k]["ms_per_step"])
     r = results[head]
     ms = r["ms_per_step"]
+    copy_gbs = copy_rate(torch)
+    log(f"[bench] device copy: {copy_gbs} GB/s (read + write)")
     line = {
         "metric": "outputs u_i/sec at rel-l2 err<=1e-6; mixed-precision vs FP64 GPU butterfly",
         "value": round(P.nx / (ms / 1e3), 1),
@@ -342,7 +362,8 @@ def main():
                    "start_level": r["info"]["start_level"]},
         "err_rel_l2": errs[head],
         "gate_passed": errs[head] is not None and errs[head] <= GATE,
-        "roofline": roofline(r, head),
+        "roofline": dict(roofline(r, head), copy_GBps=copy_gbs,
+                         frac_of_copy=round(roofline(r, head)["achieved"] / copy_gbs, 4)),
         "cpu_baseline": base,
         "precisions": {k: {"outputs_per_s": round(P.nx / (v["ms_per_step"] / 1e3), 1),
                            "ms_per_step": round(v["ms_per_step"], 4),
