@@ -91,7 +91,9 @@ void build_leaf_final(bfsft_plan *B)
                                        S->buf[S->start.s0 & 1]);
             a.first = dt;
             dp.push_back(dt);
-            dt += direct_items(S->d, S->p, a);
+            // each transform's items start on a work-group boundary (the
+            // batched kernel finds one owner per work-group)
+            dt += (direct_items(S->d, S->p, a) + 255) / 256 * 256;
             dd.push_back(a);
         }
         LeafDesc a;

@@ -289,6 +289,10 @@ __device__ __forceinline__ double2 expi_turns(double t)
 // along the last axis from sincospi, steps along axis d - 2 (G values) and
 // along the last axis (p values) by the source's per-axis phase steps, and
 // accumulates G x p outputs.
+// waves per SIMD the direct sums' registers must allow (their 3p complex
+// accumulators and phase chains): three up to p = 8, two above
+template <int P> constexpr int direct_waves() { return P <= 8 ? 3 : 2; }
+
 template <int D, int P, int G> constexpr int direct_groups() { return D == 2 ? (P + G - 1) / G : P * ((P + G - 1) / G); }
 
 template <int D, int P, int G, typename S>
@@ -302,13 +306,15 @@ __device__ __forceinline__ void direct_item(const DirectDesc &dd, int64_t gid)
     const int64_t N = dd.N, nB = dd.nB;
     if (gid >= dd.nA * nB * GL) return;
     // B-major: the threads of a wave mostly share the box B, hence the
-    // source loop's trip count and the addresses of its loads
-    const int64_t per_b = dd.nA * GL;
-    const int64_t b = gid / per_b;
-    const int64_t rem = gid - b * per_b;
-    const int64_t a = rem / GL;
-    const int grp = (int)(rem - a * GL);
-    const int64_t ab = a * nB + b;
+    // source loop's trip count and the addresses of its loads.  Item
+    // indices fit 32 bits (checked at launch).
+    const int g32 = (int)gid;
+    const int per_b = (int)dd.nA * GL;
+    const int b = g32 / per_b;
+    const int rem = g32 - b * per_b;
+    const int a = rem / GL;
+    const int grp = rem - a * GL;
+    const int64_t ab = (int64_t)a * nB + b;
     int64_t iA[3] = {0, 0, 0};
     {
         const uint64_t key = dd.xkeys[a];
@@ -380,7 +386,7 @@ __device__ __forceinline__ void direct_item(const DirectDesc &dd, int64_t gid)
 }
 
 template <int D, int P, int G, typename S>
-__global__ __launch_bounds__(256) void k_direct(DirectDesc dd)
+__global__ __launch_bounds__(256, (direct_waves<P>())) void k_direct(DirectDesc dd)
 {
     direct_item<D, P, G, S>(dd, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
@@ -408,14 +414,45 @@ __global__ __launch_bounds__(256) void k_leaf_batched(int p, const LeafDesc *__r
                     (typename CV<S>::t *)d.state, i - d.first);
 }
 
+// descriptor i, read through the constant address space (uniform: scalar
+// loads), field by field
+__device__ __forceinline__ DirectDesc load_direct_desc(const DirectDesc *descs, int i)
+{
+    using CT = const __attribute__((address_space(4))) DirectDesc;
+    CT *p = (CT *)descs + i;
+    DirectDesc d;
+    d.s0 = p->s0;
+    d.L = p->L;
+    d.N = p->N;
+    d.nA = p->nA;
+    d.nB = p->nB;
+    d.xkeys = p->xkeys;
+    d.box_leaf = p->box_leaf;
+    d.leaf_beg = p->leaf_beg;
+    d.perm = p->perm;
+    d.sm = p->sm;
+    d.sloc = p->sloc;
+    d.sstep = p->sstep;
+    d.f = p->f;
+    d.erot = p->erot;
+    d.state = p->state;
+    d.first = p->first;
+    return d;
+}
+
+// Every transform's items start on a work-group boundary (the prefix is
+// padded to 256), so the owner is uniform across a work-group: it is found
+// from the work-group's first item and its descriptor held in scalar
+// registers.
 template <int D, int P, int G, typename S>
-__global__ __launch_bounds__(256) void k_direct_batched(const DirectDesc *__restrict__ ds,
+__global__ __launch_bounds__(256, (direct_waves<P>())) void k_direct_batched(const DirectDesc *__restrict__ ds,
                                                        const int64_t *__restrict__ prefix, int n,
                                                        int64_t total)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const DirectDesc d = load_direct_desc(ds, owner(prefix, n, i0));
+    const int64_t i = i0 + threadIdx.x;
     if (i >= total) return;
-    const DirectDesc &d = ds[owner(prefix, n, i)];
     direct_item<D, P, G, S>(d, i - d.first);
 }
 
@@ -658,7 +695,9 @@ DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, co
 int64_t direct_items(int d, int p, const DirectDesc &dd)
 {
     const int ng = (p + kDirectG - 1) / kDirectG;
-    return dd.nA * dd.nB * (d == 2 ? ng : p * ng);
+    const int64_t n = dd.nA * dd.nB * (d == 2 ? ng : p * ng);
+    if (n >= ((int64_t)1 << 31)) throw Error{BFSFT_EINVAL, "start level: too many direct-sum items"};
+    return n;
 }
 
 void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
