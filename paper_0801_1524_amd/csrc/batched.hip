@@ -217,7 +217,7 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
 
     // autotuning: tile LDS budget x persistent work-groups per CU, timed on
     // the plan's own steps (results do not depend on either)
-    const std::string key = "batched2/d" + std::to_string(B->d) + "/p" + std::to_string(B->p) + "/" +
+    const std::string key = "batched3/d" + std::to_string(B->d) + "/p" + std::to_string(B->p) + "/" +
                             prec_name(B->precision) + "/n" + std::to_string(count);
     std::vector<int> best;
     if (!tune_lookup(key, best) || best.size() != 2) {
@@ -229,7 +229,7 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
             for (size_t t = 0; t < B->subs.size(); ++t)
                 if (active(B->subs[t]))
                     run_single(B->subs[t], B->f_stage + 2 * B->f_off[t], B->u_stage + 2 * B->u_off[t]);
-            for (int kb : {16, 20, 24, 32, 40}) {
+            for (int kb : {16, 20, 24, 28, 32, 36, 40}) {
                 for (bfsft_plan *S : B->subs) build_tiles(S, kb * 1024);
                 build_steps(B);
                 for (int wg : {0, 4, 5, 8}) {  // 0: one work-group per item
