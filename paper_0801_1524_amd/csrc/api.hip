@@ -111,7 +111,7 @@ namespace {
 // of their children count and size) is at most `cap`, with at most 120
 // children; a single box always fits, so every tile is non-empty.  A tile
 // record is (b0, b1, cb[b0], cb[b1]): the children range comes with it.
-std::vector<int4> make_tiles(const std::vector<int32_t> &cb, int d, int cap, int kind)
+std::vector<int4> make_tiles(const std::vector<int32_t> &cb, int d, int p, int precision, int cap, int kind)
 {
     std::vector<int4> t;
     const int n = (int)cb.size() - 1;
@@ -120,7 +120,7 @@ std::vector<int4> make_tiles(const std::vector<int32_t> &cb, int d, int cap, int
     while (b0 < n) {
         int b1 = b0 + 1;
         while (b1 < n && cb[b1 + 1] - cb[b0] <= 120 &&
-               translate_tile_cost(d, cb[b1 + 1] - cb[b0], b1 + 1 - b0, kind) <= cap)
+               translate_tile_cost(d, p, precision, cb[b1 + 1] - cb[b0], b1 + 1 - b0, kind) <= cap)
             ++b1;
         t.push_back(make_int4(b0, b1, cb[b0], cb[b1]));
         b0 = b1;
@@ -351,12 +351,12 @@ void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes, const 
         const int cap = translate_cap_blocks(P->d, P->p, P->precision, lds_bytes[l]);
         const std::vector<int32_t> &cb = P->tk.child_beg_host[l];
         const int kind = P->kind[l];
-        std::vector<int4> t = make_tiles(cb, P->d, cap, kind);
+        std::vector<int4> t = make_tiles(cb, P->d, P->p, P->precision, cap, kind);
         off[l] = all.size();
         P->ntile[l] = (int)t.size();
         for (const int4 &b : t)
             P->cost_max[l] =
-                std::max(P->cost_max[l], translate_tile_cost(P->d, cb[b.y] - cb[b.x], b.y - b.x, kind));
+                std::max(P->cost_max[l], translate_tile_cost(P->d, P->p, P->precision, cb[b.y] - cb[b.x], b.y - b.x, kind));
         P->rows[l] = translate_rows(cap, P->cost_max[l], P->tx.count[P->L - l - 1], kind);
         all.insert(all.end(), t.begin(), t.end());
     }

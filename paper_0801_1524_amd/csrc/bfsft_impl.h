@@ -114,7 +114,7 @@ struct Launch {
 
 int translate_default_lds();
 int translate_cap_blocks(int d, int p, int precision, int budget);
-int translate_tile_cost(int d, int nin, int nb, int kind = 0);
+int translate_tile_cost(int d, int p, int precision, int nin, int nb, int kind = 0);
 bool translate_fits(int d, int p, int precision);
 int translate_rows(int cap, int cost_max, int64_t nap, int kind = 0);
 size_t translate_lds_bytes(int d, int p, int precision, int rows, int cost_max, int kind = 0);

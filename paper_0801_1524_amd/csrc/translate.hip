@@ -127,16 +127,25 @@ template <typename S, typename C> struct YT { using t = typename CV<S>::t; };
 // the larger grids of p >= 10 need the full register file.
 template <int D, int P> constexpr int min_waves() { return (D == 2 && P <= 9) ? 4 : 1; }
 
+// Whether the 3D work-group holds the axis-1 results of both output
+// positions t1 at once (one box with all its children, 8 + 4 blocks, fits
+// the LDS of a work-group); otherwise one t1 at a time (8 + 2 blocks).
+template <int P, typename S> constexpr bool both3d()
+{
+    return (size_t)12 * P * P * P * sizeof(typename CV<S>::t) <= kLdsMax;
+}
+
 // Step 3, 3D (octrees, p^3 grids, axis 0 = l slowest, axis 2 = n fastest).
 // Child positions s and output positions t carry the parity of axis a in bit
-// a.  Per output position (t2 along axis 2, then t1 along axis 1):
+// a.  Per output position t2 along axis 2:
 //   stage 1 (axis 2): rows (j, l, m):  Y1 = R_t2 along n,
 //   stage 2 (axis 1): lines (b, e0, l, n): sum the children over bit 2, each
 //                     times G(e2, t2, n) (and sigma of axis 2 for e2 = 1),
-//                     then Y2[b][e0] = sum over bit 1 of G(e1, t1, .) R_t1
-//                     along m,
-//   stage 3 (axis 0): lines (b, m, n): out_t = sum over bit 0 of
+//                     then Y2[b][t1][e0] = sum over bit 1 of G(e1, t1, .)
+//                     R_t1 along m, for both t1 from the same sums,
+//   stage 3 (axis 0): lines (b, t1, m, n): out_t = sum over bit 0 of
 //                     G(e0, t0, .) R_t0 along l, written to HBM.
+// When Y2 has room for one t1 only, stages 2 and 3 run once per t1.
 template <int P, bool RHO1, typename S, typename C>
 __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, unsigned char *smem)
 {
@@ -158,8 +167,10 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     const int b0 = bt.x, nb = bt.y - bt.x;
     const int J0 = bt.z;
     const int nin = bt.w - bt.z;
+    constexpr bool BOTH = both3d<P, S>();
+    constexpr int NT1 = BOTH ? 2 : 1;       // positions t1 per stage-2 pass
     Yv *Y1 = reinterpret_cast<Yv *>(smem);  // [R][nin][P3]
-    Yv *Y2 = Y1 + R * nin * P3;             // [R][nb][2][P3]
+    Yv *Y2 = Y1 + R * nin * P3;             // [R][nb][NT1][2 e0][P3]
 
     // stage-1 rows (r, j, l, m) of the item, flattened; a thread's rows are
     // v = tid, tid + kTT, ...; loads are unconditional (clamped to the last
@@ -241,17 +252,20 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                 row_interp<P, 1, C>(Rt, x, dst);
         }
         __syncthreads();
-        for (int t1 = 0; t1 < 2; ++t1) {
-            if (!(all & (1 << (16 + 2 * t2 + t1)))) continue;
+        for (int pass = 0; pass < 2 / NT1; ++pass) {
+            // bit t1 of the positions this pass produces
+            const int mask = BOTH ? 3 : 1 << pass;
+            if (!((all >> (16 + 2 * t2)) & mask)) continue;  // uniform
             // stage 2: lines along m, for (r, b, e0, l, n)
             const int len2 = nb * 2 * P2;
             const float inv_len2 = 1.0f / (float)len2;
             for (int v = tid; v < R * len2; v += kTT) {
                 const int r = (int)(((float)v + 0.5f) * inv_len2);
-                if (!(s_bits[r] & (1 << (16 + 2 * t2 + t1)))) continue;
+                const int rn = (s_bits[r] >> (16 + 2 * t2)) & mask;
+                if (!rn) continue;
                 const int vr = v - r * len2;
                 const Yv *Yr = Y1 + r * nin * P3;
-                Yv *Y2r = Y2 + r * nb * 2 * P3;
+                Yv *Y2r = Y2 + r * nb * NT1 * 2 * P3;
                 const Cv sg1 = s_sig[r * 3 + 1], sg2 = s_sig[r * 3 + 2];
                 const int bl = vr / (2 * P2);
                 const int rem = vr - bl * 2 * P2;
@@ -282,29 +296,38 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
 #pragma unroll
                     for (int m = 0; m < P; ++m) z1[m] = cmul(z1[m], sg1);
                 }
-                Yv *dst = Y2r + (bl * 2 + e0) * P3 + l * P2 + n;
-                if (t1 == 0)
+                // Y2r[bl][t1][e0]
+                Yv *dst = Y2r + (bl * NT1 * 2 + e0) * P3 + l * P2 + n;
+                if (BOTH) {
+                    if (rn & 1) line_interp<P, 0, C>(Rt, Ct, z0, z1, dst, P);
+                    if (rn & 2) line_interp<P, 1, C>(Rt, Ct, z0, z1, dst + 2 * P3, P);
+                } else if (pass == 0) {
                     line_interp<P, 0, C>(Rt, Ct, z0, z1, dst, P);
-                else
+                } else {
                     line_interp<P, 1, C>(Rt, Ct, z0, z1, dst, P);
+                }
             }
             __syncthreads();
-            // stage 3: lines along l, for (r, b, m, n); both output positions t0
-            const int len3 = nb * P2;
+            // stage 3: lines along l, for (r, b, t1, m, n); both output positions t0
+            const int len3 = nb * NT1 * P2;
             const float inv_len3 = 1.0f / (float)len3;
             for (int v = tid; v < R * len3; v += kTT) {
                 const int r = (int)(((float)v + 0.5f) * inv_len3);
                 const int bits = s_bits[r];
-                if (!(bits & (1 << (16 + 2 * t2 + t1)))) continue;
                 const int vr = v - r * len3;
-                const Yv *Y2r = Y2 + r * nb * 2 * P3;
+                const int bl = vr / (NT1 * P2);
+                const int rem = vr - bl * NT1 * P2;
+                const int k = BOTH ? rem / P2 : 0;
+                const int mn = rem - k * P2;
+                const int t1 = BOTH ? k : pass;
+                if (!(bits & (1 << (16 + 2 * t2 + t1)))) continue;
+                const Yv *Y2r = Y2 + r * nb * NT1 * 2 * P3;
                 const Cv sg0 = s_sig[r * 3 + 0];
                 const int ta = 4 * t2 + 2 * t1;
                 const int a0 = s_out[r * 8 + ta], a1 = s_out[r * 8 + ta + 1];
-                const int bl = vr / P2, mn = vr - bl * P2;
                 Cv z0[P], z1[P];
-                const Yv *y0 = Y2r + (bl * 2 + 0) * P3 + mn;
-                const Yv *y1 = Y2r + (bl * 2 + 1) * P3 + mn;
+                const Yv *y0 = Y2r + ((bl * NT1 + k) * 2 + 0) * P3 + mn;
+                const Yv *y1 = y0 + P3;
                 const bool h1 = (s_cj[bl * 8 + 1] >= 0) | (s_cj[bl * 8 + 3] >= 0) |
                                 (s_cj[bl * 8 + 5] >= 0) | (s_cj[bl * 8 + 7] >= 0);
                 const bool h0 = (s_cj[bl * 8 + 0] >= 0) | (s_cj[bl * 8 + 2] >= 0) |
@@ -626,6 +649,15 @@ int lds_budget_default()
 
 int translate_default_lds() { return lds_budget_default(); }
 
+// Blocks of axis-1 results per box of a 3D tile: both t1 (4) when a box
+// with all its children fits that way, else one t1 (2); the kernels take
+// the same decision from their template arguments (both3d)
+static int y2_blocks(int p, int precision)
+{
+    const size_t elem = precision == BFSFT_FP64 ? 16 : 8;
+    return (size_t)12 * p * p * p * elem <= kLdsMax ? 4 : 2;
+}
+
 // LDS blocks (p^d elements of the intermediate type) a work-group may hold
 // within `budget` bytes
 int translate_cap_blocks(int d, int p, int precision, int budget)
@@ -634,7 +666,7 @@ int translate_cap_blocks(int d, int p, int precision, int budget)
     for (int a = 1; a < d; ++a) PD *= p;
     const int elem = precision == BFSFT_FP64 ? 16 : 8;
     int cap = budget / (PD * elem);
-    const int one_box = d == 2 ? 2 * 4 : 8 + 2;  // a single box with all children
+    const int one_box = d == 2 ? 2 * 4 : 8 + y2_blocks(p, precision);  // a single box with all children
     if (cap < one_box) cap = one_box;
     return cap;
 }
@@ -642,10 +674,10 @@ int translate_cap_blocks(int d, int p, int precision, int budget)
 // LDS blocks a tile of nb boxes with nin children needs: the VALU kernels
 // hold the axis-2 results (2D: both t2) or two stages (3D); the matrix-core
 // kernel also stages the input blocks
-int translate_tile_cost(int d, int nin, int nb, int kind)
+int translate_tile_cost(int d, int p, int precision, int nin, int nb, int kind)
 {
     if (kind == 1) return 3 * nin;
-    return d == 2 ? 2 * nin : nin + 2 * nb;
+    return d == 2 ? 2 * nin : nin + y2_blocks(p, precision) * nb;
 }
 
 bool translate_fits(int d, int p, int precision)
@@ -653,7 +685,7 @@ bool translate_fits(int d, int p, int precision)
     int PD = p;
     for (int a = 1; a < d; ++a) PD *= p;
     const int elem = precision == BFSFT_FP64 ? 16 : 8;
-    const int one_box = d == 2 ? 2 * 4 : 8 + 2;
+    const int one_box = d == 2 ? 2 * 4 : 8 + y2_blocks(p, precision);
     return (size_t)one_box * PD * elem <= kLdsMax;
 }
 
