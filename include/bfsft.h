@@ -87,7 +87,9 @@ typedef struct {
  *   N          frequency bound, 2 <= N <= 2^24 (2D) or 2^16 (3D).
  *   p          equivalent-grid size per axis (Section 2.1), 3 <= p <= 12 in
  *              2D, 3 <= p <= 8 in 3D (p = 2 makes the matching system
- *              singular).
+ *              singular); 3D p = 8 needs BFSFT_MIXED or BFSFT_FP32 (the
+ *              FP64 state of one box and its children exceeds a work-group's
+ *              LDS): BFSFT_EINVAL otherwise.
  *   precision  BFSFT_FP64, BFSFT_MIXED or BFSFT_FP32.
  *   x, nx      device, [nx][d] targets in [0, N]^d; nx >= 0 (NULL iff nx == 0).
  *   k, nk      device, [nk][d] sources in [0, N]^d; nk >= 0 (NULL iff nk == 0).

@@ -49,6 +49,7 @@ def test_strerror_and_destroy_null(lib):
     (2, 256, 2, 0),      # p = 2: singular matching system
     (2, 256, 13, 0),     # p beyond the 2D tile bound
     (3, 256, 9, 0),      # p beyond the 3D tile bound
+    (3, 256, 8, 0),      # 3D p = 8 at FP64: one box and its children exceed the LDS
     (2, 1, 5, 0),        # N < 2
     (2, 256, 5, 7),      # unknown precision
 ])

@@ -218,6 +218,18 @@ def test_3d_fp64_vs_oracle(bf, oracle_mod, p):
     assert rel_l2(gpu_u(bf, P), oracle_u(oracle_mod, P)) <= 1e-10
 
 
+@pytest.mark.parametrize("N,p,precision", [(16, 7, "fp64"), (24, 7, "fp64"), (16, 7, "mixed"),
+                                             (24, 8, "mixed"), (16, 8, "fp32")])
+def test_3d_large_p_both_lds_layouts(bf, oracle_mod, N, p, precision):
+    """p = 7 at FP64 holds one axis-1 position t1 at a time in LDS (both
+    do not fit); the FP32-state paths hold both up to p = 8."""
+    x = synth.sphere(N)
+    k = synth.sphere(N, radius=0.3)
+    f = synth.gaussian_sources(k.shape[0], N + p)
+    P = synth.Problem("sphp", 3, N, p, x, k, f)
+    assert rel_l2(gpu_u(bf, P, precision), oracle_u(oracle_mod, P)) <= TOL_O2[precision]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_3d_sphere_vs_oracle_and_direct(bf, oracle_mod, precision):
     N, p = 32, 5
