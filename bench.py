@@ -303,8 +303,8 @@ def main():
         summarize_counters(*args.summarize_counters, args.precisions.split(",")[0], COUNTERS)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sharding of a "
+              "transform across GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
