@@ -178,6 +178,26 @@ def curve_problem(N, p, seed=0, shape="c1"):
     return Problem(f"curves-N{N}", 2, N, p, x, k, gaussian_sources(k.shape[0], seed))
 
 
+def sparse_problem(d, N, p, n, seed):
+    """n targets and n sources drawn at random on closed surfaces far too
+    large to sample at one point per unit (the largest N a plan accepts):
+    2D circle r = 0.4 (targets) and r(t) = 0.3 + 0.08 cos 3t (sources); 3D
+    spheres r = 0.4 and 0.3; uniform in angle (3D: in area), seeded."""
+    rng = np.random.default_rng(seed)
+    if d == 2:
+        t = rng.uniform(0.0, 2.0 * np.pi, size=(2, n))
+        r = np.stack([np.full(n, 0.4), 0.3 + 0.08 * np.cos(3.0 * t[1])])
+        pts = [np.stack([0.5 + r[i] * np.cos(t[i]), 0.5 + r[i] * np.sin(t[i])], 1) for i in range(2)]
+    else:
+        z = rng.uniform(-1.0, 1.0, size=(2, n))
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=(2, n))
+        rad = (0.4, 0.3)
+        pts = [0.5 + rad[i] * np.stack([np.sqrt(1 - z[i] ** 2) * np.cos(ph[i]),
+                                        np.sqrt(1 - z[i] ** 2) * np.sin(ph[i]), z[i]], 1) for i in range(2)]
+    x, k = (np.clip(q * N, 0.0, float(N)) for q in pts)
+    return Problem(f"sparse{d}-N{N}", d, N, p, x, k, gaussian_sources(n, seed))
+
+
 def batched_config(count=256, p=7, nmin=512, nmax=16384, seed=5000):
     """Batched workload: independent 2D transforms of uneven N.
 

@@ -181,3 +181,21 @@ def test_batched_auto_start_vs_serial_and_direct(bf, oracle_mod, monkeypatch):
     assert rel_l2(ug, us) <= 1e-14
     for q, u in zip(probs, _split(ug, probs)):
         assert rel_l2(u, oracle_mod.direct(q.x, q.k, q.f, q.N)) <= EPS[7], (q.name, q.N)
+
+
+@pytest.mark.parametrize("d,N,p,n,precision,start", [
+    (2, 1 << 24, 7, 1000, "fp64", 0), (2, 1 << 24, 7, 1000, "fp64", None),
+    (2, 1 << 24, 7, 1000, "mixed", None), (3, 1 << 16, 5, 400, "fp64", 0),
+    (3, 1 << 16, 5, 400, "fp64", None)])
+def test_largest_N(bf, oracle_mod, monkeypatch, d, N, p, n, precision, start):
+    """The largest frequency bound a plan accepts (2^24 in 2D, 2^16 in 3D:
+    24 and 16 levels), with a few hundred points per side at random on
+    closed curves and spheres: every output against the direct sum at the
+    method's accuracy, and at FP64 sampled targets against the oracle
+    butterfly at the same start level (exactly their ancestor pairs)."""
+    P = synth.sparse_problem(d, N, p, n, seed=N + p)
+    u, s0 = run(bf, P, precision, start, monkeypatch)
+    assert rel_l2(u, oracle_mod.direct(P.x, P.k, P.f, P.N)) <= EPS[p]
+    if precision == "fp64":
+        T = np.arange(0, P.nx, 40 if d == 2 else 25)
+        assert rel_l2(u[T], oracle_u(oracle_mod, P, s0, x=P.x[T])) <= 1e-10

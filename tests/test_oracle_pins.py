@@ -127,6 +127,17 @@ def test_butterfly_vs_direct_configs(oracle_mod, name):
     assert rel_l2(u[S], oracle_mod.direct(P.x, P.k, P.f, P.N, S)) < EPS_BOUND[P.p]
 
 
+@pytest.mark.parametrize("d,N,p,n,step", [(2, 1 << 24, 7, 1000, 40), (3, 1 << 16, 5, 400, 25)])
+def test_butterfly_vs_direct_at_the_largest_N(oracle_mod, d, N, p, n, step):
+    """The largest N a plan accepts (24 and 16 levels), sparse random points:
+    the butterfly keeps the accuracy set by p (Theorem 2.1 does not depend
+    on N or on where the points lie in their boxes)."""
+    P = synth.sparse_problem(d, N, p, n, seed=N + p)
+    T = np.arange(0, P.nx, step)
+    u = oracle_mod.Butterfly(d, N, p, P.x[T], P.k).run(P.f)
+    assert rel_l2(u, oracle_mod.direct(P.x[T], P.k, P.f, N)) < EPS_BOUND[p]
+
+
 @pytest.mark.parametrize("N,p", [(1024, 5), (1024, 7), (1024, 9), (4096, 5), (4096, 7), (4096, 9)])
 def test_butterfly_matches_paper_table1(oracle_mod, N, p):
     """Ellipses (Section 3, Table 1): same accuracy regime as the printed eps_a."""
