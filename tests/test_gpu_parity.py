@@ -87,6 +87,21 @@ def test_level_potentials_vs_oracle(bf, oracle_mod, level_frac):
     assert rel_l2(pot, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("N", [2, 3, 5])
+@pytest.mark.parametrize("p", [3, 5])
+def test_smallest_N(bf, oracle_mod, d, N, p):
+    """N = 2 (one level), 3 and 5 (rho = 0.75, 0.625), 40 random points per
+    side in [0, N]^d."""
+    rng = np.random.default_rng(11 * N + p + d)
+    x = rng.uniform(0, N, (40, d))
+    k = rng.uniform(0, N, (40, d))
+    P = synth.Problem("tiny", d, N, p, x, k, synth.gaussian_sources(40, p))
+    u = gpu_u(bf, P)
+    assert rel_l2(u, oracle_u(oracle_mod, P)) <= 1e-10
+    assert rel_l2(u, oracle_mod.direct(x, k, P.f, N)) <= EPS[p]
+
+
 def test_deterministic(bf):
     P = synth.config("c1")
     with bf.Plan(P.d, P.N, P.p, P.x, P.k, "fp64") as plan:

@@ -105,7 +105,7 @@ def test_direct_subset_is_subset(oracle_mod):
 
 # --------------------------------------------------------------------- O2 ---
 
-@pytest.mark.parametrize("N", [4, 8, 16, 32])
+@pytest.mark.parametrize("N", [2, 3, 4, 8, 16, 32])
 @pytest.mark.parametrize("p", [3, 5, 7, 9])
 def test_butterfly_brute_force_tiny(oracle_mod, N, p):
     rng = np.random.default_rng(7 * N + p)
