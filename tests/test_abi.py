@@ -71,4 +71,12 @@ def test_negative_count_and_null_points_rejected(lib):
 def test_execute_null_plan(lib):
     assert lib.bfsft_execute(None, None, None) == -1
     assert lib.bfsft_execute_batched(None, None, None) == -1
+
+
+def test_batched_without_problems_rejected(lib):
+    h = ctypes.c_void_p(1234)
+    assert lib.bfsft_plan_create_batched(ctypes.byref(h), 0, None, 2, 5, 0, None) == -1
+    assert h.value is None
+    assert lib.bfsft_plan_create_batched(ctypes.byref(h), 3, None, 2, 5, 0, None) == -1
+    assert lib.bfsft_last_error()
     assert lib.bfsft_execute_adjoint(None, None, None) == -1

@@ -73,6 +73,23 @@ def test_graph_replays_agree(bf):
     assert rel_l2(ug, us) <= 1e-14
 
 
+def test_batched_single_and_all_empty(bf):
+    """A batch of one transform matches the single-transform plan; a batch
+    whose members all lack sources (or targets) gives zeros (or nothing)."""
+    q = small_batch(count=1, seed=9)[0]
+    B = bf.BatchedPlan([(q.N, q.x, q.k)], 2, 7, "fp64")
+    ub = B.execute(q.f).cpu().numpy()
+    B.close()
+    with bf.Plan(2, q.N, 7, q.x, q.k, "fp64") as plan:
+        us = plan.execute(q.f).cpu().numpy()
+    assert rel_l2(ub, us) <= 1e-14
+    nok = [(300, synth.circle(300), np.zeros((0, 2))), (200, synth.circle(200), np.zeros((0, 2)))]
+    B = bf.BatchedPlan(nok, 2, 7, "mixed")
+    u = B.execute(np.zeros(0, complex)).cpu().numpy()
+    B.close()
+    assert u.shape[0] == sum(x.shape[0] for _, x, _ in nok) and not np.any(u)
+
+
 def test_batched_with_empty_transforms(bf):
     probs = small_batch(count=3, seed=5)
     empty_k = synth.Problem("nok", 2, 300, 7, synth.circle(300), np.zeros((0, 2)), np.zeros(0, complex))
