@@ -22,29 +22,36 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bfsft_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# another build of this source to load instead (the mutation tests point it
+# at copies with one planted mistake each); never rebuilt here
+_SO_OVERRIDE = os.environ.get("BFSFT_ORACLE_LIB")
 _lib = None
 
 __all__ = ["build", "direct", "direct_numpy", "Butterfly", "threads"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp%d" % os.getpid()
+def build(force: bool = True, src: str = _SRC, out: str = _SO) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math); `src` and
+    `out` default to this package's source and library."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-            "-fcx-limited-range", "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+            "-fcx-limited-range", "-fno-fast-math", "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = ctypes.CDLL(_SO)
+    if _SO_OVERRIDE:
+        lib = ctypes.CDLL(_SO_OVERRIDE)
+    else:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_SO)
     P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     D = ctypes.c_double
     lib.or_direct.argtypes = [I, D, P, P, P, I64, P, I64, P]
