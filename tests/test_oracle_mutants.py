@@ -38,6 +38,11 @@ MUTANTS = [
     ("back substitution transposed", "for (int j = i + 1; j < p; ++j) b[i * s] -= LU[i * p + j] * b[j * s];",
      "for (int j = i + 1; j < p; ++j) b[i * s] -= LU[j * p + i] * b[j * s];"),
     ("axis operator transposed", "acc += A[l * p + m] * fib[m];", "acc += A[m * p + l] * fib[m];"),
+    # steps 2 and 4 of Section 2.2
+    ("step 2 axis index", "ph[s][l] = expi_dd(dd_div(two_prod((double)(q * iA[s] + l), kj[s]), qs));",
+     "ph[s][l] = expi_dd(dd_div(two_prod((double)(q * iA[s] + l), kj[0]), qs));"),
+    ("step 4 axis order", "for (int s = d - 1; s >= 0; --s) { w *= ph[s][r % p]; r /= p; }\n                acc += w;",
+     "for (int s = 0; s < d; ++s) { w *= ph[s][r % p]; r /= p; }\n                acc += w;"),
 ]
 
 
