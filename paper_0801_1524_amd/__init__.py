@@ -7,6 +7,17 @@ There is no CPU fallback: importing the binding without the built library,
 or using it without a GPU, raises.
 
     u_i = sum_j exp(2 pi i x_i . k_j / N) f_j        (Section 1, eq. 1)
+
+Usage (points as [n][d] float64 arrays in [0, N]^d, numpy or torch; sources
+complex128; results are complex128 tensors on the current GPU)::
+
+    import paper_0801_1524_amd as bf
+    with bf.Plan(2, N, 9, x, k, "mixed") as plan:   # trees, tables, tuning
+        u = plan.execute(f)                          # steps 2-4 of Section 2.2
+        v = plan.execute_adjoint(g)                  # sum_i exp(-2 pi i x_i . k_j / N) g_i
+    B = bf.BatchedPlan([(N1, x1, k1), (N2, x2, k2)], 2, 7, "mixed")
+    u_packed = B.execute(f_packed)                   # one graph for all transforms
+    B.close()
 """
 from __future__ import annotations
 
