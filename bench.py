@@ -131,11 +131,12 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(precision):
+def traffic_from_profile(precision, workload):
     """HBM bytes per translation launch from committed rocprofv3 counter
     summaries (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel calibration),
-    or None if absent or taken on a different kernel source."""
-    if not os.path.exists(COUNTERS):
+    or None if absent, taken on a different kernel source, or taken on
+    another workload (the counters are of the c2 run)."""
+    if workload != "c2" or not os.path.exists(COUNTERS):
         return None
     try:
         rec = json.load(open(COUNTERS))
@@ -239,14 +240,14 @@ def copy_rate(torch):
     return round(rate, 1)
 
 
-def roofline(res, precision):
+def roofline(res, precision, workload):
     info, tm = res["info"], res["timing"]
     nlev = info["levels"] - info["start_level"]                   # translation launches per execute
     launches = nlev * tm["executes"]
     t_avg = sum(tm["translate_ms"]) / launches / 1e3           # s per launch
     bytes_avg = info["sweep_bytes"] / nlev                        # algorithmic bytes per launch
     achieved = bytes_avg / t_avg / 1e9
-    traffic = traffic_from_profile(precision)
+    traffic = traffic_from_profile(precision, workload)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
@@ -295,6 +296,10 @@ def main():
                          "(FETCH_SIZE, WRITE_SIZE) to profiles/ and exit")
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"],
                     help="c2 (default) is the configuration the metric is quoted on")
+    ap.add_argument("--N", type=int, default=None,
+                    help="instead of --workload: c2's curve family (circle r=0.4 targets, "
+                         "r=0.3+0.08cos3t sources, 1 sample per unit length, p=9) at this N; "
+                         "no oracle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -323,9 +328,18 @@ def main():
         del src, dst
         log("[bench] calibration copy: 1073741824 bytes read, 1073741824 bytes written")
 
-    P = synth.config(args.workload)
-    S = synth.error_subset(P.nx, synth.CONFIG_NAMES.index(args.workload))
-    log(f"[bench] workload {args.workload}: d={P.d} nx={P.nx} nk={P.nk} N={P.N} p={P.p}")
+    if args.N:
+        P = synth.curve_problem(args.N, 9, seed=args.N)
+        S = None
+        args.no_cpu = True
+        wl = f"curves-N{args.N}"
+        wl_text = (f"2D sparse FT, N={args.N}, p=9, circle r=0.4 targets / r=0.3+0.08cos3t sources, "
+                   "1 sample per unit length")
+    else:
+        P = synth.config(args.workload)
+        S = synth.error_subset(P.nx, synth.CONFIG_NAMES.index(args.workload))
+        wl, wl_text = args.workload, WORKLOADS[args.workload]
+    log(f"[bench] workload {wl}: d={P.d} nx={P.nx} nk={P.nk} N={P.N} p={P.p}")
     results = {}
     for prec in args.precisions.split(","):
         results[prec] = time_precision(bf, torch, P, prec, args.steps, args.warmup)
@@ -356,14 +370,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head in ("fp64", "mixed") else "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
+        "config": {"workload": wl_text,
                    "nx": P.nx, "nk": P.nk, "levels": r["info"]["levels"], "precision": head,
                    "state_dtype": "f64" if head == "fp64" else "f32",
                    "start_level": r["info"]["start_level"]},
         "err_rel_l2": errs[head],
         "gate_passed": errs[head] is not None and errs[head] <= GATE,
-        "roofline": dict(roofline(r, head), copy_GBps=copy_gbs,
-                         frac_of_copy=round(roofline(r, head)["achieved"] / copy_gbs, 4)),
+        "roofline": dict(roofline(r, head, wl), copy_GBps=copy_gbs,
+                         frac_of_copy=round(roofline(r, head, wl)["achieved"] / copy_gbs, 4)),
         "cpu_baseline": base,
         "precisions": {k: {"outputs_per_s": round(P.nx / (v["ms_per_step"] / 1e3), 1),
                            "ms_per_step": round(v["ms_per_step"], 4),
@@ -371,7 +385,7 @@ def main():
                            # leaf initialisation, or the direct sums of a start above the leaves
                            "start_ms_per_step": round(v["timing"]["leaf_ms"] / v["timing"]["executes"], 4),
                            "err_rel_l2": errs[k],
-                           "roofline_frac": roofline(v, k)["frac"]}
+                           "roofline_frac": roofline(v, k, wl)["frac"]}
                        for k, v in results.items()},
     }
     if "fp64" in results and head != "fp64":

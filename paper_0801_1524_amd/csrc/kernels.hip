@@ -611,7 +611,13 @@ __global__ void k_zero_c128(double2 *u, int64_t n)
     if (i < n) u[i] = make_double2(0.0, 0.0);
 }
 
-inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
+// blocks of t threads covering n items; a launch must stay below 2^32
+// work-items (a larger one would run only part of its grid)
+inline int nblk(int64_t n, int t)
+{
+    if (n > ((int64_t)1 << 32) - t) throw Error{BFSFT_EINVAL, "a launch would exceed 2^32 work-items"};
+    return (int)((n + t - 1) / t);
+}
 
 }  // namespace
 

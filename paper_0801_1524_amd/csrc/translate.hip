@@ -566,17 +566,17 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
 // One work item per work-group (single transform).
 
 template <int P, bool RHO1, typename S, typename C>
-__global__ __launch_bounds__(kTT, (min_waves<2, P>())) void k_translate2d(TArgs a)
+__global__ __launch_bounds__(kTT, (min_waves<2, P>())) void k_translate2d(TArgs a, int64_t item0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    translate2d_item<P, RHO1, S, C>(a, blockIdx.x, smem);
+    translate2d_item<P, RHO1, S, C>(a, item0 + blockIdx.x, smem);
 }
 
 template <int P, bool RHO1, typename S, typename C>
-__global__ __launch_bounds__(kTT) void k_translate3d(TArgs a)
+__global__ __launch_bounds__(kTT) void k_translate3d(TArgs a, int64_t item0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    translate3d_item<P, RHO1, S, C>(a, blockIdx.x, smem);
+    translate3d_item<P, RHO1, S, C>(a, item0 + blockIdx.x, smem);
 }
 
 // Persistent batched step: the work items of all transforms still active at
@@ -622,10 +622,10 @@ __global__ __launch_bounds__(kTT, (min_waves<D, P>())) void k_translate_batched(
 template <int D, int P, typename S, typename C>
 __global__ __launch_bounds__(kTT, (min_waves<D, P>())) void k_translate_batched_flat(const TArgs *__restrict__ descs,
                                                                   const int64_t *__restrict__ prefix,
-                                                                  int ndesc)
+                                                                  int ndesc, int64_t item0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t item = blockIdx.x;
+    const int64_t item = item0 + blockIdx.x;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -738,16 +738,21 @@ void launch_translate(const Launch &c, const LevelArgs &la)
         constexpr int P = decltype(tag)::value;
         using S = std::remove_pointer_t<decltype(sp)>;
         using C = std::remove_pointer_t<decltype(cp)>;
-        if constexpr (decltype(d3)::value) {
-            if (la.sig)
-                k_translate3d<P, false, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
-            else
-                k_translate3d<P, true, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
-        } else {
-            if (la.sig)
-                k_translate2d<P, false, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
-            else
-                k_translate2d<P, true, S, C><<<(unsigned)grid, kTT, lds, c.stream>>>(a);
+        // chunks of at most kMaxGroups work-groups (see kMaxGroups)
+        const int64_t chunk = max_groups();
+        for (int64_t i0 = 0; i0 < grid; i0 += chunk) {
+            const unsigned g = (unsigned)std::min<int64_t>(chunk, grid - i0);
+            if constexpr (decltype(d3)::value) {
+                if (la.sig)
+                    k_translate3d<P, false, S, C><<<g, kTT, lds, c.stream>>>(a, i0);
+                else
+                    k_translate3d<P, true, S, C><<<g, kTT, lds, c.stream>>>(a, i0);
+            } else {
+                if (la.sig)
+                    k_translate2d<P, false, S, C><<<g, kTT, lds, c.stream>>>(a, i0);
+                else
+                    k_translate2d<P, true, S, C><<<g, kTT, lds, c.stream>>>(a, i0);
+            }
         }
     };
     if (c.d == 2)
@@ -773,8 +778,10 @@ void launch_translate_batched(const Launch &c, const void *descs, const int64_t 
         using S = std::remove_pointer_t<decltype(sp)>;
         using C = std::remove_pointer_t<decltype(cp)>;
         if (grid <= 0)
-            k_translate_batched_flat<D, P, S, C><<<(unsigned)total, kTT, lds, c.stream>>>(
-                (const TArgs *)descs, prefix, ndesc);
+            for (int64_t i0 = 0, chunk = max_groups(); i0 < total; i0 += chunk)  // see kMaxGroups
+                k_translate_batched_flat<D, P, S, C>
+                    <<<(unsigned)std::min<int64_t>(chunk, total - i0), kTT, lds, c.stream>>>(
+                        (const TArgs *)descs, prefix, ndesc, i0);
         else
             k_translate_batched<D, P, S, C><<<g, kTT, lds, c.stream>>>((const TArgs *)descs, prefix, ndesc,
                                                                        total, next);

@@ -6,6 +6,8 @@
 #include "bfsft_impl.h"
 #include "cplx.h"
 
+#include <cstdlib>
+
 namespace bfsft {
 namespace tr {
 
@@ -17,6 +19,19 @@ constexpr int kWaves = kTT / 64;
 constexpr int kRowsMax = 32;   // rows a' per work-group
 constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
 constexpr size_t kLdsMax = 60 * 1024;  // dynamic LDS of one work-group (static use stays below 4 KB)
+// Work-groups of one launch: its work-items (work-groups x kTT) must stay
+// below 2^32, or the dispatch runs only part of the grid.  Launches of more
+// work items are split into chunks of this many, each told its first item.
+constexpr int64_t kMaxGroups = (((int64_t)1 << 32) / kTT) - 1;
+
+// chunk size of the translation launches: kMaxGroups, or less when
+// BFSFT_MAX_GROUPS asks for it (tests of the chunked launches)
+inline int64_t max_groups()
+{
+    const char *e = std::getenv("BFSFT_MAX_GROUPS");
+    const long long v = e ? std::atoll(e) : 0;
+    return v >= 1 && v < kMaxGroups ? (int64_t)v : kMaxGroups;
+}
 
 struct TArgs {
     const void *in;

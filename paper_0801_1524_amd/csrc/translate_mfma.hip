@@ -142,7 +142,7 @@ __global__ void k_mfma_tables(int p, const double2 *__restrict__ L64, const doub
 }
 
 template <int P, bool RHO1, typename S>
-__global__ __launch_bounds__(kTT) void k_translate2d_mfma(TArgs a, const double *__restrict__ mt)
+__global__ __launch_bounds__(kTT) void k_translate2d_mfma(TArgs a, const double *__restrict__ mt, int64_t item0)
 {
     constexpr MShape M(P);
     constexpr int PP = P * P, Q = P - 1, ND = M.ND, NC = M.NC, KS1 = M.KS1, NB = M.NB, REM = M.REM;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kTT) void k_translate2d_mfma(TArgs a, const double 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4, j16 = lane & 15;
     if (tid < P) s_nph[tid] = make_double2(mt[M.oNPH + 2 * tid], mt[M.oNPH + 2 * tid + 1]);
     if (tid < 2 * P) s_cf[tid] = make_double2(mt[M.oCF + 2 * tid], mt[M.oCF + 2 * tid + 1]);
-    const Item2D it = setup2d<double2>(a, blockIdx.x, s_out, s_bits, s_sig, s_pos,
+    const Item2D it = setup2d<double2>(a, item0 + blockIdx.x, s_out, s_bits, s_sig, s_pos,
                                        reinterpret_cast<signed char *>(s_cj4));
     const int R = it.R, nb = it.nb, nin = it.nin;
     const int nblk = R * nin;
@@ -398,16 +398,21 @@ void launch_translate_mfma(const Launch &c, const LevelArgs &la)
     if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
     dispatch_p59(c.p, [&](auto tag) {
         constexpr int P = decltype(tag)::value;
-        if (c.precision == BFSFT_FP64) {
-            if (la.sig)
-                k_translate2d_mfma<P, false, double><<<(unsigned)grid, kTT, lds, c.stream>>>(a, c.tb->mf);
-            else
-                k_translate2d_mfma<P, true, double><<<(unsigned)grid, kTT, lds, c.stream>>>(a, c.tb->mf);
-        } else {
-            if (la.sig)
-                k_translate2d_mfma<P, false, float><<<(unsigned)grid, kTT, lds, c.stream>>>(a, c.tb->mf);
-            else
-                k_translate2d_mfma<P, true, float><<<(unsigned)grid, kTT, lds, c.stream>>>(a, c.tb->mf);
+        // chunks of at most kMaxGroups work-groups (see kMaxGroups)
+        const int64_t chunk = max_groups();
+        for (int64_t i0 = 0; i0 < grid; i0 += chunk) {
+            const unsigned g = (unsigned)std::min<int64_t>(chunk, grid - i0);
+            if (c.precision == BFSFT_FP64) {
+                if (la.sig)
+                    k_translate2d_mfma<P, false, double><<<g, kTT, lds, c.stream>>>(a, c.tb->mf, i0);
+                else
+                    k_translate2d_mfma<P, true, double><<<g, kTT, lds, c.stream>>>(a, c.tb->mf, i0);
+            } else {
+                if (la.sig)
+                    k_translate2d_mfma<P, false, float><<<g, kTT, lds, c.stream>>>(a, c.tb->mf, i0);
+                else
+                    k_translate2d_mfma<P, true, float><<<g, kTT, lds, c.stream>>>(a, c.tb->mf, i0);
+            }
         }
     });
     BF_HIP(hipGetLastError());

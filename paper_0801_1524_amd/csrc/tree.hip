@@ -239,7 +239,13 @@ __global__ void k_slots(const uint64_t *__restrict__ child_keys, const int32_t *
     slots[b] = w;
 }
 
-inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
+// blocks of t threads covering n items; a launch must stay below 2^32
+// work-items (a larger one would run only part of its grid)
+inline int nblk(int64_t n, int t)
+{
+    if (n > ((int64_t)1 << 32) - t) throw Error{BFSFT_EINVAL, "a launch would exceed 2^32 work-items"};
+    return (int)((n + t - 1) / t);
+}
 
 uint32_t read_count(const uint32_t *flags, const uint32_t *pos, int n, hipStream_t s)
 {

@@ -90,6 +90,22 @@ def test_batched_single_and_all_empty(bf):
     assert u.shape[0] == sum(x.shape[0] for _, x, _ in nok) and not np.any(u)
 
 
+def test_batched_chunked_launches(bf, monkeypatch):
+    """The batched step launches split into chunks of 7 work-groups give the
+    same bits as single launches (same tuned choices, read from the cache)."""
+    probs = small_batch(count=4, seed=13)
+    f = packed(probs)
+    monkeypatch.delenv("BFSFT_MAX_GROUPS", raising=False)
+    B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, "mixed")
+    u_one = B.execute(f).cpu().numpy()
+    B.close()
+    monkeypatch.setenv("BFSFT_MAX_GROUPS", "7")
+    B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, "mixed")
+    u_chunked = B.execute(f).cpu().numpy()
+    B.close()
+    assert np.array_equal(u_one, u_chunked)
+
+
 def test_batched_with_empty_transforms(bf):
     probs = small_batch(count=3, seed=5)
     empty_k = synth.Problem("nok", 2, 300, 7, synth.circle(300), np.zeros((0, 2)), np.zeros(0, complex))

@@ -102,6 +102,25 @@ def test_smallest_N(bf, oracle_mod, d, N, p):
     assert rel_l2(u, oracle_mod.direct(x, k, P.f, N)) <= EPS[p]
 
 
+@pytest.mark.parametrize("d,kernel", [(2, "valu"), (2, "mfma"), (3, "valu")])
+def test_chunked_launches_match_one_launch(bf, monkeypatch, d, kernel):
+    """A level's work-groups launched in chunks, each told its first item
+    (as a launch beyond 2^32 work-items must be split), give the same bits as
+    one launch.  BFSFT_MAX_GROUPS makes the chunks small here."""
+    if d == 2:
+        P = synth.config("c1")
+        monkeypatch.setenv("BFSFT_TRANSLATE", kernel)
+    else:
+        x = synth.sphere(32)
+        P = synth.Problem("sph32", 3, 32, 5, x, x.copy(), synth.gaussian_sources(x.shape[0], 3))
+    monkeypatch.setenv("BFSFT_AUTOTUNE", "0")  # the same tiles in both runs
+    monkeypatch.delenv("BFSFT_MAX_GROUPS", raising=False)
+    u_one = gpu_u(bf, P)
+    monkeypatch.setenv("BFSFT_MAX_GROUPS", "7")
+    u_chunked = gpu_u(bf, P)
+    assert np.array_equal(u_one, u_chunked)
+
+
 def test_deterministic(bf):
     P = synth.config("c1")
     with bf.Plan(P.d, P.N, P.p, P.x, P.k, "fp64") as plan:
