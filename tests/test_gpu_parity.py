@@ -240,6 +240,20 @@ def test_c2_full_size_vs_oracle_sampled_targets(bf, oracle_mod, c2):
     assert rel_l2(u[S], ub) <= 1e-10
 
 
+def test_dense_N_2_22_sampled(bf, oracle_mod, monkeypatch):
+    """C2's curve family at N = 2^22, one sample per unit length (10.5 M
+    targets, 9.1 M sources, 22 levels, about 24 GB of mixed state per level;
+    its translation launches are split into chunks when tiles are small):
+    64 sampled outputs of the mixed path against the direct sum at the
+    1e-6 gate, with the plan's own start level."""
+    monkeypatch.setenv("BFSFT_AUTOTUNE", "0")
+    monkeypatch.delenv("BFSFT_START_LEVEL", raising=False)
+    P = synth.curve_problem(1 << 22, 9, seed=22)
+    u = gpu_u(bf, P, "mixed")
+    S = np.sort(np.random.default_rng(22).choice(P.nx, 64, replace=False))
+    assert rel_l2(u[S], oracle_mod.direct(P.x, P.k, P.f, P.N, S)) <= 1e-6
+
+
 # ----------------------------------------------------------------------- 3D
 
 @pytest.mark.parametrize("p", [3, 4, 5, 6])
