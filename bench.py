@@ -7,8 +7,10 @@ accuracy can meet the 1e-6 gate): 2D, N = 65536, p = 9; targets on the circle
 centre (0.5, 0.5) radius 0.4, sources on the curve r = 0.3 + 0.08 cos 3t,
 both scaled by N at one sample per unit length (164,710 targets, 141,644
 sources); complex Gaussian sources.  A step is one execute of the planned
-transform: leaf initialisation, the 16 translation levels and the final
-evaluation, with points, plan and sources resident in HBM.
+transform: the direct sums of the start level the plan chooses (4 levels
+above the leaves at this size, in place of the leaf initialisation), the 12
+remaining translation levels and the final evaluation, with points, plan and
+sources resident in HBM.  --N runs the same curve family at another N.
 
 Every precision ("mixed": FP32 state, FP64 arithmetic; "fp64"; "fp32") is
 timed with the same K/W; the headline value is the fastest one whose error on
