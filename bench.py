@@ -12,7 +12,9 @@ above the leaves at this size, in place of the leaf initialisation), the 12
 remaining translation levels and the final evaluation, with points, plan and
 sources resident in HBM.  --N runs the same curve family at another N.
 
-Every precision ("mixed": FP32 state, FP64 arithmetic; "fp64"; "fp32") is
+Every precision ("mixed": FP32 state, FP64 arithmetic; "fp64"; "fp32";
+"fp16x2" and "bf16x3": FP32 state, the axis-2 contractions on the matrix
+cores as split FP16 / BF16 products with FP32 accumulation, the rest FP64) is
 timed with the same K/W; the headline value is the fastest one whose error on
 the 2000-output subset passes the gate.  The error check and the CPU
 baseline (the oracle butterfly on the host cores, one full transform) form
@@ -116,6 +118,8 @@ def bench_batched(args, torch, bf, synth):
     }
     print(json.dumps(line), flush=True)
 GATE = 1e-6
+# arithmetic of each precision's sweep (leaf, phases and evaluation are FP64 in all)
+DTYPE = {"fp64": "f64", "mixed": "f64", "fp32": "f32", "fp16x2": "f16x2", "bf16x3": "bf16x3"}
 COUNTERS = os.path.join(ROOT, "profiles", "translate_c2_counters.json")
 # sources of the translation kernels (the counters are valid while these are unchanged)
 KERNEL_SRC = [os.path.join(ROOT, "paper_0801_1524_amd", "csrc", f)
@@ -133,11 +137,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(precision, workload):
-    """HBM bytes per translation launch from committed rocprofv3 counter
-    summaries (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel calibration),
-    or None if absent, taken on a different kernel source, or taken on
-    another workload (the counters are of the c2 run)."""
+def counters_from_profile(precision, workload):
+    """Counter summary of the translation kernel (per launch) from the
+    committed rocprofv3 runs, or None if absent, taken on a different kernel
+    source, or taken on another workload (the counters are of the c2 run)."""
     if workload != "c2" or not os.path.exists(COUNTERS):
         return None
     try:
@@ -146,22 +149,30 @@ def traffic_from_profile(precision, workload):
         return None
     if rec.get("kernel_sha") != kernel_hash():
         return None
-    ent = rec.get("precisions", {}).get(precision)
-    if not ent:
-        return None
-    return ent.get("bytes_per_launch")
+    return rec.get("precisions", {}).get(precision)
 
 
-def summarize_counters(fetch_dir, write_dir, precision, out_path):
-    """HBM traffic of the translation kernel from two rocprofv3 --pmc runs of
-    `bench.py --calib` (one with FETCH_SIZE, one with WRITE_SIZE).  Each
-    counter (KiB per dispatch) is scaled by what it reads for the 1 GiB
-    calibration copy, which moves exactly 2^30 bytes each way."""
+# VALU instruction counters of the third pass (one --pmc run, 8 SQ counters)
+VALU_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
+                 "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
+                 "SQ_INSTS_VALU", "SQ_INSTS_MFMA"]
+
+
+def summarize_counters(fetch_dir, write_dir, valu_dir, precision, out_path):
+    """Per-launch counters of the translation kernel from rocprofv3 --pmc runs
+    of `bench.py --calib`: HBM traffic from FETCH_SIZE and WRITE_SIZE (one
+    run each; each counter, in KiB per dispatch, is scaled by what it reads
+    for the 1 GiB calibration copy, which moves exactly 2^30 bytes each way)
+    and, if valu_dir is given, the VALU arithmetic instructions of
+    VALU_COUNTERS (one run)."""
     import csv
 
-    def load(d, counter):
-        rows = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
+    def rows_of(d, counter):
+        return [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
                 if r["Counter_Name"] == counter]
+
+    def load(d, counter):
+        rows = rows_of(d, counter)
         tr = [float(r["Counter_Value"]) for r in rows if "k_translate" in r["Kernel_Name"]]
         other = [float(r["Counter_Value"]) for r in rows if "bfsft" not in r["Kernel_Name"]]
         return tr, max(other)
@@ -172,6 +183,18 @@ def summarize_counters(fetch_dir, write_dir, precision, out_path):
     fw = (1 << 30) / (wcopy * 1024.0)
     fetch = sum(ftr) / len(ftr) * 1024.0 * ff
     write = sum(wtr) / len(wtr) * 1024.0 * fw
+    valu = None
+    if valu_dir:
+        valu = {}
+        for c in VALU_COUNTERS:
+            v = [float(r["Counter_Value"]) for r in rows_of(valu_dir, c) if "k_translate" in r["Kernel_Name"]]
+            valu[c] = sum(v) / len(v)
+        # flops issued: 64 lanes per wave instruction (an upper bound on the
+        # flops executed: inactive lanes of an instruction are counted too)
+        valu["issued_flops_f64"] = 64.0 * (2 * valu["SQ_INSTS_VALU_FMA_F64"] + valu["SQ_INSTS_VALU_MUL_F64"]
+                                           + valu["SQ_INSTS_VALU_ADD_F64"])
+        valu["issued_flops_f32"] = 64.0 * (2 * valu["SQ_INSTS_VALU_FMA_F32"] + valu["SQ_INSTS_VALU_MUL_F32"]
+                                           + valu["SQ_INSTS_VALU_ADD_F32"])
     rec = {}
     if os.path.exists(out_path):
         try:
@@ -180,14 +203,16 @@ def summarize_counters(fetch_dir, write_dir, precision, out_path):
             rec = {}
     if rec.get("kernel_sha") != kernel_hash():
         rec = {"kernel_sha": kernel_hash(), "precisions": {}}
+    cmd = f"python bench.py --precisions {precision} --steps 3 --warmup 1 --no-cpu --calib"
     rec["precisions"][precision] = {
         "bytes_per_launch": round(fetch + write), "fetch_bytes_per_launch": round(fetch),
         "write_bytes_per_launch": round(write), "launches": len(ftr),
         "calibration": {"fetch_factor": ff, "write_factor": fw},
-        "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- "
-                     f"python bench.py --precisions {precision} --steps 3 --warmup 1 --no-cpu --calib",
-                     f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- "
-                     f"python bench.py --precisions {precision} --steps 3 --warmup 1 --no-cpu --calib"],
+        "valu_per_launch": valu,
+        "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- {cmd}",
+                     f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- {cmd}"]
+        + ([f"rocprofv3 --pmc {' '.join(VALU_COUNTERS)} --output-format csv -d {valu_dir} -o run -- {cmd}"]
+           if valu_dir else []),
     }
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -224,22 +249,16 @@ def time_precision(bf, torch, P, precision, steps, warmup):
     return {"ms_per_step": ms, "timing": tm, "info": info, "u": out}
 
 
-def copy_rate(torch):
-    """GB/s (bytes read + written) of a plain 1 GiB device-to-device copy on
-    the same GPU, timed over 5 copies after one untimed: the practical
-    streaming bandwidth, beside the 8 TB/s peak.  Outside the timed region."""
-    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    rate = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del src, dst
-    return round(rate, 1)
+def copy_rate(bf, elem_bytes):
+    """GB/s (bytes read + written) of the library's plain streaming copy
+    kernel over 1 GiB, at the state's element size, 5 timed copies after one
+    untimed: the practical memory ceiling beside the 8 TB/s peak.  Outside
+    the timed region."""
+    return round(bf.copy_rate(elem_bytes, 1 << 30, 5), 1)
+
+
+# vector peaks of MI355X (TFLOP/s): FP64 and FP32 (no packed FP32 is generated)
+PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 78.6}
 
 
 def roofline(res, precision, workload):
@@ -249,21 +268,44 @@ def roofline(res, precision, workload):
     t_avg = sum(tm["translate_ms"]) / launches / 1e3           # s per launch
     bytes_avg = info["sweep_bytes"] / nlev                        # algorithmic bytes per launch
     achieved = bytes_avg / t_avg / 1e9
-    traffic = traffic_from_profile(precision, workload)
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
-            # counter bytes per launch over the same launch time (null without counters)
-            "traffic_GBps": None if traffic is None else round(traffic / t_avg / 1e9, 1),
-            "kernel": "k_translate2d" if info["d"] == 2 else "k_translate3d", "avg_launch_ms": round(t_avg * 1e3, 4),
-            "alg_bytes_per_launch": bytes_avg,
-            "alg_flops_per_launch": info["sweep_flops"] / nlev,
-            "alg_tflops": round(info["sweep_flops"] / nlev / t_avg / 1e12, 2)}
+    cnt = counters_from_profile(precision, workload)
+    traffic = cnt.get("bytes_per_launch") if cnt else None
+    valu = cnt.get("valu_per_launch") if cnt else None
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4),
+           "traffic": traffic,
+           # counter bytes per launch over the same launch time (null without counters)
+           "traffic_GBps": None if traffic is None else round(traffic / t_avg / 1e9, 1),
+           "kernel": "k_translate2d" if info["d"] == 2 else "k_translate3d", "avg_launch_ms": round(t_avg * 1e3, 4),
+           "alg_bytes_per_launch": bytes_avg,
+           # the separable method's flop count (48 p^3 per pair in 2D, 112 p^4 in 3D): a model
+           # figure, not executed work (the kernels skip the copy rows and use real operators)
+           "model_flops_per_launch": info["sweep_flops"] / nlev}
+    if valu:
+        # VALU arithmetic issued per launch (rocprofv3 counters x 64 lanes) over the launch time
+        dt = "f32" if precision == "fp32" else "f64"
+        fl = valu["issued_flops_" + dt]
+        out["valu_issued"] = {"dtype": dt, "flops_per_launch": fl, "tflops": round(fl / t_avg / 1e12, 2),
+                              "peak_tflops": PEAK_VALU_TFLOPS[dt],
+                              "frac": round(fl / t_avg / 1e12 / PEAK_VALU_TFLOPS[dt], 4)}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline_leg(P, gpu_results, S):
-    """The oracle: direct sum on the error subset (the accuracy gate of every
-    GPU result) and one full oracle butterfly timed on the host cores."""
+    """The oracle: the direct sum on the error subset (the accuracy gate of
+    every GPU result) and one full oracle butterfly timed on the host cores,
+    run at the start level of the GPU plans so that every GPU output can be
+    compared with it element by element."""
     import oracle
     oracle.build(force=False)
     t = time.perf_counter()
@@ -273,17 +315,27 @@ def cpu_baseline_leg(P, gpu_results, S):
     for prec, r in gpu_results.items():
         errs[prec] = float(np.linalg.norm(r["u"][S] - ud) / np.linalg.norm(ud))
         log(f"[bench] {prec}: rel-l2 vs direct sum on {len(S)} outputs = {errs[prec]:.3e}")
+    s0s = {r["info"]["start_level"] for r in gpu_results.values()}
+    s0 = min(s0s)
     cores = oracle.threads()
-    log(f"[bench] oracle butterfly on {cores} threads (full transform) ...")
+    log(f"[bench] oracle butterfly on {cores} threads (full transform, start level {s0}) ...")
     B = oracle.Butterfly(P.d, P.N, P.p, P.x, P.k)
     t = time.perf_counter()
-    B.run(P.f)
+    ub = B.run(P.f, start_level=s0)
     t_bf = time.perf_counter() - t
     log(f"[bench] oracle butterfly {t_bf:.2f} s")
+    vs_oracle = {}
+    for prec, r in gpu_results.items():
+        if r["info"]["start_level"] == s0:
+            vs_oracle[prec] = float(np.linalg.norm(r["u"] - ub) / np.linalg.norm(ub))
+            log(f"[bench] {prec}: rel-l2 vs oracle butterfly (all {P.nx} outputs) = {vs_oracle[prec]:.3e}")
     base = {"value": round(P.nx / t_bf, 1), "unit": "outputs/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full transform of the same workload ({P.nx} outputs), f-form butterfly (long double)",
+            "cpu_model": cpu_model(),
+            "sample": f"one full transform of the same workload ({P.nx} outputs), f-form butterfly "
+                      f"(long double), start level {s0} as the GPU plans",
             "seconds": round(t_bf, 3),
-            "direct_sum_est_seconds": round(t_direct * P.nx / len(S), 2)}
+            "direct_sum_est_seconds": round(t_direct * P.nx / len(S), 2),
+            "rel_l2_vs_oracle": vs_oracle}
     return base, errs
 
 
@@ -292,10 +344,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precisions", default="mixed,fp64,fp32")
-    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write the translation kernel's HBM traffic from two rocprofv3 --pmc runs "
-                         "(FETCH_SIZE, WRITE_SIZE) to profiles/ and exit")
+    ap.add_argument("--precisions", default="mixed,fp64,fp32,fp16x2,bf16x3")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="FETCH_DIR WRITE_DIR [VALU_DIR]: write the translation kernel's per-launch "
+                         "counters from rocprofv3 --pmc runs (FETCH_SIZE; WRITE_SIZE; the VALU "
+                         "instruction counters) to profiles/ and exit")
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"],
                     help="c2 (default) is the configuration the metric is quoted on")
     ap.add_argument("--N", type=int, default=None,
@@ -307,7 +360,8 @@ def main():
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters, args.precisions.split(",")[0], COUNTERS)
+        dirs = list(args.summarize_counters) + [None]
+        summarize_counters(dirs[0], dirs[1], dirs[2], args.precisions.split(",")[0], COUNTERS)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sharding of a "
@@ -357,8 +411,9 @@ def main():
     head = min(passing, key=lambda k: results[k]["ms_per_step"])
     r = results[head]
     ms = r["ms_per_step"]
-    copy_gbs = copy_rate(torch)
-    log(f"[bench] device copy: {copy_gbs} GB/s (read + write)")
+    elem = 16 if head == "fp64" else 8
+    copy_gbs = copy_rate(bf, elem)
+    log(f"[bench] streaming copy kernel ({elem} B elements): {copy_gbs} GB/s (read + write)")
     line = {
         "metric": "outputs u_i/sec at rel-l2 err<=1e-6; mixed-precision vs FP64 GPU butterfly",
         "value": round(P.nx / (ms / 1e3), 1),
@@ -370,7 +425,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head in ("fp64", "mixed") else "f32",
+        "dtype": DTYPE[head],
         "data": "synthetic",
         "config": {"workload": wl_text,
                    "nx": P.nx, "nk": P.nk, "levels": r["info"]["levels"], "precision": head,
@@ -378,7 +433,7 @@ def main():
                    "start_level": r["info"]["start_level"]},
         "err_rel_l2": errs[head],
         "gate_passed": errs[head] is not None and errs[head] <= GATE,
-        "roofline": dict(roofline(r, head, wl), copy_GBps=copy_gbs,
+        "roofline": dict(roofline(r, head, wl), copy_GBps=copy_gbs, copy_elem_bytes=elem,
                          frac_of_copy=round(roofline(r, head, wl)["achieved"] / copy_gbs, 4)),
         "cpu_baseline": base,
         "precisions": {k: {"outputs_per_s": round(P.nx / (v["ms_per_step"] / 1e3), 1),

@@ -42,11 +42,21 @@ extern "C" {
 #define BFSFT_ENOMEM   -3   /* device allocation failed or BFSFT_MAX_DEVICE_BYTES exceeded */
 #define BFSFT_EDEVICE  -4   /* a HIP runtime call failed (message in bfsft_last_error) */
 
-/* Arithmetic of the translation sweep.  Leaf initialisation, phases and the
- * final evaluation always run in FP64; inputs and outputs are complex128. */
-#define BFSFT_FP64   0  /* FP64 state in HBM, FP64 arithmetic                */
-#define BFSFT_MIXED  1  /* FP32 state in HBM, FP64 arithmetic in registers   */
-#define BFSFT_FP32   2  /* FP32 state in HBM, FP32 arithmetic                */
+/* Arithmetic of the translation sweep (step 3 of Section 2.2).  Leaf
+ * initialisation, phases and the final evaluation always run in FP64; inputs
+ * and outputs are complex128.  The split formats apply the axis-2
+ * interpolation of every level (the per-axis contraction of Section 2.1,
+ * eq. (E1)) on the matrix cores, accumulating in FP32, and do the rest of the
+ * level (children sums with their phases, axis-1 interpolation, output
+ * phases) in FP64; they are 2D only (BFSFT_EINVAL in 3D). */
+#define BFSFT_FP64    0  /* FP64 state in HBM, FP64 arithmetic                     */
+#define BFSFT_FP32    1  /* FP32 state in HBM, FP32 arithmetic (VALU, or the axis-2
+                            contraction on FP32 matrix cores, tuned per level)     */
+#define BFSFT_FP16X2  2  /* FP32 state; axis-2 contraction as FP16 hi + lo split
+                            products (three per term, each line scaled by 2^e)     */
+#define BFSFT_BF16X3  3  /* FP32 state; axis-2 contraction as exact three-term BF16
+                            split products (six per term)                          */
+#define BFSFT_MIXED   4  /* FP32 state in HBM, FP64 arithmetic in registers        */
 
 #define BFSFT_MAX_LEVELS 32
 
@@ -73,7 +83,9 @@ typedef struct {
     int wg_per_cu;                        /* batched: persistent work-groups per CU (tuned); 0: one
                                              work-group per work item instead */
     int level_kernel[BFSFT_MAX_LEVELS];   /* single plan, translation producing T_K level l:
-                                             0 VALU kernel, 1 matrix-core (MFMA) kernel */
+                                             0 VALU kernel, 1 FP64 matrix-core kernel, 2 axis-2
+                                             contraction on the matrix cores in the precision's
+                                             format (FP32, FP16X2, BF16X3) */
     int level_lds_kb[BFSFT_MAX_LEVELS];   /* single plan: tile LDS budget of level l (tuned) */
     int start_level;                      /* single plan: the sweep starts at T_K level
                                              levels - start_level (0: at the leaves) */
@@ -90,7 +102,8 @@ typedef struct {
  *              singular); 3D p = 8 needs BFSFT_MIXED or BFSFT_FP32 (the
  *              FP64 state of one box and its children exceeds a work-group's
  *              LDS): BFSFT_EINVAL otherwise.
- *   precision  BFSFT_FP64, BFSFT_MIXED or BFSFT_FP32.
+ *   precision  BFSFT_FP64, BFSFT_FP32, BFSFT_FP16X2 (2D), BFSFT_BF16X3 (2D)
+ *              or BFSFT_MIXED; any other value is BFSFT_EINVAL.
  *   x, nx      device, [nx][d] targets in [0, N]^d; nx >= 0 (NULL iff nx == 0).
  *   k, nk      device, [nk][d] sources in [0, N]^d; nk >= 0 (NULL iff nk == 0).
  *   stream     hipStream_t (NULL = default stream) used for all work of the plan.
@@ -101,10 +114,11 @@ typedef struct {
  * Environment: BFSFT_MAX_DEVICE_BYTES caps the plan's device memory;
  * BFSFT_AUTOTUNE=0 disables the plan-time tuning of the translation tiles
  * (otherwise the sweep is timed on the plan's own shapes for a few tile LDS
- * budgets and, in 2D with 5 <= p <= 9 and FP64 arithmetic, for both the
- * VALU and the matrix-core translation kernel, and the fastest is kept per
- * level; results differ between the choices only by rounding);
- * BFSFT_TRANSLATE=valu or =mfma restricts the kernel to one of the two;
+ * budgets and, in 2D, for every translation kernel the precision allows: with
+ * FP64 arithmetic (5 <= p <= 9) the VALU and the FP64 matrix-core kernel, in
+ * FP32 the VALU kernel and the FP32 matrix-core axis-2 contraction; the
+ * fastest is kept per level; results differ between the choices only by
+ * rounding); BFSFT_TRANSLATE=valu, =mfma or =xdl restricts the choice to one;
  * the sweep starts start_level levels above the leaves of T_K, where the
  * potentials of every pair are summed directly over the sources of B (the
  * plain procedure of Section 2.1), with start_level chosen from the tree
@@ -168,9 +182,10 @@ int bfsft_execute_probe(bfsft_plan *plan, const double *f, double *u,
  * shares the plan's trees and tables.
  *   g  device, nx complex128 (interleaved), indexed like x.
  *   v  device, nk complex128, overwritten; must not alias g.
- * The first call on a plan builds the adjoint's tiles and state buffers
- * (device allocation, tuning, stream synchronisation); later calls only
- * enqueue work on the plan's stream.  nx = 0 gives v = 0.
+ * The adjoint's tiles, start level and input staging are built with the
+ * plan, and it shares the plan's state buffers (executes of one plan are
+ * stream-ordered), so a call only enqueues work on the plan's stream and
+ * allocates nothing.  nx = 0 gives v = 0.
  */
 int bfsft_execute_adjoint(bfsft_plan *plan, const double *g, double *v);
 
@@ -219,6 +234,17 @@ int bfsft_execute_batched_serial(bfsft_plan *plan, const double *f_packed, doubl
  */
 int bfsft_timing_begin(bfsft_plan *plan, int max_execs);
 int bfsft_timing_end(bfsft_plan *plan, double *out, int n);
+
+/*
+ * Measurement helper (not part of the method): the streaming bandwidth of a
+ * plain device copy kernel, the practical memory ceiling the translation
+ * kernels are compared with.  Allocates two device buffers of `bytes` each,
+ * runs one untimed and `reps` timed copies of elements of `elem_bytes`
+ * (4, 8 or 16) on `stream`, frees the buffers and writes to *gbps (host) the
+ * bytes read plus written per second / 1e9.  bytes must be a multiple of
+ * elem_bytes in [2^20, 2^34].  Synchronises the stream.
+ */
+int bfsft_copy_rate(int elem_bytes, int64_t bytes, int reps, void *stream, double *gbps);
 
 #ifdef __cplusplus
 }

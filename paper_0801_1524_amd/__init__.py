@@ -30,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfsft.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE = 0, -1, -2, -3, -4
-PRECISIONS = {"fp64": 0, "mixed": 1, "fp32": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x2": 2, "bf16x3": 3, "mixed": 4}
 MAX_LEVELS = 32
 
 _lib = None
@@ -101,6 +101,8 @@ def lib():
     L.bfsft_timing_begin.restype = I
     L.bfsft_timing_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), I]
     L.bfsft_timing_end.restype = I
+    L.bfsft_copy_rate.argtypes = [I, I64, I, P, ctypes.POINTER(ctypes.c_double)]
+    L.bfsft_copy_rate.restype = I
     _lib = L
     return L
 
@@ -131,8 +133,53 @@ def _dev_complex(a, torch):
     return a.to(device="cuda", dtype=torch.complex128).contiguous().reshape(-1)
 
 
-def _stream(torch):
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+def _sources(a, n, torch, what):
+    """Device complex128 copy (or view) of a source vector, of exactly n values."""
+    t = _dev_complex(a, torch)
+    if t.numel() != n:
+        raise ValueError(f"{what} has {t.numel()} values, the plan expects {n}")
+    return t
+
+
+def _output(out, n, torch, what):
+    """A caller's output tensor, checked, or a new one: complex128, contiguous,
+    on the current GPU, with at least n values (the kernels write n)."""
+    if out is None:
+        return torch.empty(n, dtype=torch.complex128, device="cuda")
+    if not isinstance(out, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if out.dtype != torch.complex128 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous complex128 tensor on the GPU")
+    if out.device.index != torch.cuda.current_device():
+        raise ValueError(f"{what} is on another GPU than the current one")
+    if out.numel() < n:
+        raise ValueError(f"{what} has {out.numel()} values, the plan writes {n}")
+    return out
+
+
+class _Ordered:
+    """Runs a call on the plan's stream in order with the caller's current
+    stream: the plan stream waits for the current one (the inputs were made
+    there), the current one waits for the plan stream afterwards (the
+    outputs are read there), and tensors used on both are recorded on the
+    plan stream so the caching allocator does not reuse them early."""
+
+    def __init__(self, torch, plan_stream, tensors):
+        self.torch, self.ps, self.tensors = torch, plan_stream, tensors
+
+    def __enter__(self):
+        self.cur = self.torch.cuda.current_stream()
+        self.other = self.cur.cuda_stream != self.ps.cuda_stream
+        if self.other:
+            self.ps.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, *exc):
+        if self.other:
+            self.cur.wait_stream(self.ps)
+            for t in self.tensors:
+                if t is not None and t.numel():
+                    t.record_stream(self.ps)
 
 
 def _info_dict(info: Info) -> dict:
@@ -154,7 +201,9 @@ class Plan:
     """A planned transform for fixed targets x (nx, d) and sources k (nk, d).
 
     ``precision``: "fp64" (FP64 state and arithmetic), "mixed" (FP32 state in
-    HBM, FP64 arithmetic) or "fp32" (FP32 state and arithmetic).
+    HBM, FP64 arithmetic) or "fp32" (FP32 state and arithmetic).  Every
+    execute runs on the stream that was current at creation, ordered with
+    the caller's current stream.
     """
 
     def __init__(self, d, N, p, x, k, precision="fp64"):
@@ -165,11 +214,15 @@ class Plan:
         xd = _dev_points(x, d, torch)
         kd = _dev_points(k, d, torch)
         self.nx, self.nk = int(xd.shape[0]), int(kd.shape[0])
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        # every execute runs on this stream, ordered with the caller's current one
+        self._stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
         rc = self._L.bfsft_plan_create(ctypes.byref(h), self.d, self.N, self.p, PRECISIONS[precision],
                                        ctypes.c_void_p(xd.data_ptr() if self.nx else 0), self.nx,
                                        ctypes.c_void_p(kd.data_ptr() if self.nk else 0), self.nk,
-                                       _stream(torch))
+                                       ctypes.c_void_p(self._stream.cuda_stream))
         _check(rc)
         self._h = h
 
@@ -190,20 +243,22 @@ class Plan:
     def execute(self, f, out=None):
         """u (complex128 device tensor, original target order) for sources f."""
         torch = _torch()
-        fd = _dev_complex(f, torch)
-        u = out if out is not None else torch.empty(self.nx, dtype=torch.complex128, device="cuda")
-        _check(self._L.bfsft_execute(self._h, ctypes.c_void_p(fd.data_ptr() if self.nk else 0),
-                                     ctypes.c_void_p(u.data_ptr() if self.nx else 0)))
+        fd = _sources(f, self.nk, torch, "f")
+        u = _output(out, self.nx, torch, "out")
+        with _Ordered(torch, self._stream, (fd, u)):
+            _check(self._L.bfsft_execute(self._h, ctypes.c_void_p(fd.data_ptr() if self.nk else 0),
+                                         ctypes.c_void_p(u.data_ptr() if self.nx else 0)))
         return u
 
     def execute_adjoint(self, g, out=None):
         """v_j = sum_i exp(-2 pi i x_i . k_j / N) g_i (complex128 device tensor,
         original source order) for values g at the targets."""
         torch = _torch()
-        gd = _dev_complex(g, torch)
-        v = out if out is not None else torch.empty(self.nk, dtype=torch.complex128, device="cuda")
-        _check(self._L.bfsft_execute_adjoint(self._h, ctypes.c_void_p(gd.data_ptr() if self.nx else 0),
-                                             ctypes.c_void_p(v.data_ptr() if self.nk else 0)))
+        gd = _sources(g, self.nx, torch, "g")
+        v = _output(out, self.nk, torch, "out")
+        with _Ordered(torch, self._stream, (gd, v)):
+            _check(self._L.bfsft_execute_adjoint(self._h, ctypes.c_void_p(gd.data_ptr() if self.nx else 0),
+                                                 ctypes.c_void_p(v.data_ptr() if self.nk else 0)))
         return v
 
     def execute_probe(self, f, level):
@@ -213,12 +268,13 @@ class Plan:
         info = self.info()
         L = info["levels"]
         nA, nB = info["x_boxes"][L - level], info["k_boxes"][level]
-        fd = _dev_complex(f, torch)
+        fd = _sources(f, self.nk, torch, "f")
         u = torch.empty(self.nx, dtype=torch.complex128, device="cuda")
         pot = torch.empty((nA, nB, self.p ** self.d), dtype=torch.complex128, device="cuda")
-        _check(self._L.bfsft_execute_probe(self._h, ctypes.c_void_p(fd.data_ptr()),
-                                           ctypes.c_void_p(u.data_ptr()), int(level),
-                                           ctypes.c_void_p(pot.data_ptr())))
+        with _Ordered(torch, self._stream, (fd, u, pot)):
+            _check(self._L.bfsft_execute_probe(self._h, ctypes.c_void_p(fd.data_ptr()),
+                                               ctypes.c_void_p(u.data_ptr()), int(level),
+                                               ctypes.c_void_p(pot.data_ptr())))
         return u, pot
 
     def info(self) -> dict:
@@ -270,9 +326,12 @@ class BatchedPlan:
             arr[i].nk = kd.shape[0]
             self.nx_list.append(int(xd.shape[0]))
             self.nk_list.append(int(kd.shape[0]))
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self._stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
         rc = self._L.bfsft_plan_create_batched(ctypes.byref(h), len(problems), arr, self.d, self.p,
-                                               PRECISIONS[precision], _stream(torch))
+                                               PRECISIONS[precision], ctypes.c_void_p(self._stream.cuda_stream))
         self._keep = []
         _check(rc)
         self._h = h
@@ -289,16 +348,28 @@ class BatchedPlan:
 
     def execute(self, f_packed, out=None, serial=False):
         torch = _torch()
-        fd = _dev_complex(f_packed, torch)
-        u = out if out is not None else torch.empty(self.nx, dtype=torch.complex128, device="cuda")
+        fd = _sources(f_packed, self.nk, torch, "f_packed")
+        u = _output(out, self.nx, torch, "out")
         fn = self._L.bfsft_execute_batched_serial if serial else self._L.bfsft_execute_batched
-        _check(fn(self._h, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(u.data_ptr())))
+        with _Ordered(torch, self._stream, (fd, u)):
+            _check(fn(self._h, ctypes.c_void_p(fd.data_ptr() if self.nk else 0),
+                      ctypes.c_void_p(u.data_ptr() if self.nx else 0)))
         return u
 
     def info(self) -> dict:
         info = Info()
         _check(self._L.bfsft_plan_info(self._h, ctypes.byref(info)))
         return _info_dict(info)
+
+
+def copy_rate(elem_bytes: int = 8, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s (read + write) of the library's plain streaming copy kernel on
+    the current GPU and stream: the practical memory ceiling."""
+    torch = _torch()
+    out = ctypes.c_double()
+    _check(lib().bfsft_copy_rate(int(elem_bytes), int(nbytes), int(reps),
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(out)))
+    return out.value
 
 
 def transform(x, k, f, N, p, d=None, precision="fp64"):

@@ -15,8 +15,6 @@
 
 namespace bfsft {
 
-int validate_points(const double *pts, int64_t n, int d, int64_t N, hipStream_t s);
-
 // batched.hip
 void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs);
 void execute_batched(bfsft_plan *B, const double *f, double *u, bool serial);
@@ -52,6 +50,43 @@ void Arena::release()
     for (void *p : ptrs) (void)hipFree(p);
     ptrs.clear();
     bytes = 0;
+}
+
+void *Arena::alloc_temp(size_t n)
+{
+    if (n == 0) n = 16;
+    n = (n + 255) & ~(size_t)255;
+    if (cap >= 0 && bytes + temp_bytes + (int64_t)n > cap)
+        throw Error{BFSFT_ENOMEM, "BFSFT_MAX_DEVICE_BYTES exceeded by plan-time temporaries (" +
+                                      std::to_string(bytes + temp_bytes + n) + " > " + std::to_string(cap) + ")"};
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{BFSFT_ENOMEM, std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e)};
+    }
+    temp_bytes += (int64_t)n;
+    return p;
+}
+
+void Arena::free_temp(void *p, size_t n)
+{
+    if (n == 0) n = 16;
+    n = (n + 255) & ~(size_t)255;
+    (void)hipFree(p);
+    temp_bytes -= (int64_t)n;
+}
+
+void *TempList::alloc(size_t n)
+{
+    void *q = arena.alloc_temp(n);
+    p.emplace_back(q, n);
+    return q;
+}
+
+TempList::~TempList()
+{
+    for (auto &e : p) arena.free_temp(e.first, e.second);
 }
 
 int ceil_log2(int64_t N)
@@ -149,8 +184,11 @@ void check_scalars(int d, int64_t N, int p, int precision, int64_t nx, int64_t n
                    const void *k)
 {
     if (d != 2 && d != 3) throw Error{BFSFT_EINVAL, "d must be 2 or 3"};
-    if (precision != BFSFT_FP64 && precision != BFSFT_MIXED && precision != BFSFT_FP32)
+    if (precision != BFSFT_FP64 && precision != BFSFT_MIXED && precision != BFSFT_FP32 &&
+        !split_precision(precision))
         throw Error{BFSFT_EINVAL, "unknown precision"};
+    if (split_precision(precision) && d != 2)
+        throw Error{BFSFT_EINVAL, "the FP16X2 and BF16X3 contraction formats are 2D only"};
     const int pmax = d == 2 ? 12 : 8;
     if (p < 3 || p > pmax)
         throw Error{BFSFT_EINVAL, "p must be in [3, " + std::to_string(pmax) + "] for d = " + std::to_string(d)};
@@ -182,7 +220,13 @@ void init_plan(bfsft_plan *P, int d, int64_t N, int p, int precision, int64_t nx
 
 const char *prec_name(int precision)
 {
-    return precision == BFSFT_FP64 ? "fp64" : precision == BFSFT_MIXED ? "mixed" : "fp32";
+    switch (precision) {
+    case BFSFT_FP64: return "fp64";
+    case BFSFT_FP32: return "fp32";
+    case BFSFT_FP16X2: return "fp16x2";
+    case BFSFT_BF16X3: return "bf16x3";
+    default: return "mixed";
+    }
 }
 
 size_t state_bytes(const bfsft_plan *P)
@@ -223,18 +267,28 @@ std::vector<double> time_levels(bfsft_plan *P, int reps)
     return best;
 }
 
-// Kernels the tuner may use for this plan: bit 0 the VALU kernel, bit 1 the
-// matrix-core kernel; BFSFT_TRANSLATE=valu or =mfma restricts the choice.
+// Kernels the tuner may use for this plan: bit k allows kind k (0 the VALU
+// kernel, 1 the FP64 matrix-core kernel, 2 stage 1 on the matrix cores in
+// the precision's contraction format).  The split formats have only kind 2;
+// otherwise BFSFT_TRANSLATE=valu, =mfma or =xdl restricts the choice to one
+// kind where the plan allows it.  Members of a batched plan use the VALU
+// kernel (kind 2 for the split formats).
 int kernel_choices(const bfsft_plan *P)
 {
+    if (split_precision(P->precision)) return 4;
     int m = 1;
     if (!P->valu_only && translate_mfma_supported(P->d, P->p, P->precision)) m |= 2;
+    if (!P->valu_only && translate_xdl_supported(P->d, P->p, P->precision)) m |= 4;
     if (const char *s = std::getenv("BFSFT_TRANSLATE")) {
         if (std::strcmp(s, "valu") == 0) m &= 1;
         else if (std::strcmp(s, "mfma") == 0 && (m & 2)) m = 2;
+        else if (std::strcmp(s, "xdl") == 0 && (m & 4)) m = 4;
     }
     return m;
 }
+
+// the kind of a single choice (untuned plans): the lowest allowed
+int first_kind(int choices) { return (choices & 1) ? 0 : (choices & 2) ? 1 : 2; }
 
 // Choose the kernel and the tile LDS budget of every level of a single plan
 // by timing the sweep on the plan's own shapes.  Neither changes what is
@@ -265,8 +319,8 @@ void autotune_single(bfsft_plan *P)
     // budgets a few KB apart: the threads a tile fills depend on them finely
     const int cand[] = {8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 54, 60};
     std::vector<double> best(P->L, 1e30);
-    std::vector<int> pick(P->L, 32), pk(P->L, 0);
-    for (int kind = 0; kind < 2; ++kind) {
+    std::vector<int> pick(P->L, 32), pk(P->L, first_kind(choices));
+    for (int kind = 0; kind < 3; ++kind) {
         if (!(choices & (1 << kind))) continue;
         for (int kb : cand) {
             build_tiles_levels(P, std::vector<int>(P->L, kb * 1024), std::vector<int>(P->L, kind));
@@ -288,8 +342,11 @@ void autotune_single(bfsft_plan *P)
     tune_store(key, store);
 }
 
-void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot)
+// Steps 2-4 for sources f into u.  The two state buffers are the plan's own
+// unless `bufs` names others (each at least state_bytes(P)).
+void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot, void *const *bufs = nullptr)
 {
+    void *const B[2] = {bufs ? bufs[0] : P->buf[0], bufs ? bufs[1] : P->buf[1]};
     if (P->nx == 0) return;
     if (P->nk == 0) {
         launch_zero_c128(u, P->nx, P->stream);
@@ -302,25 +359,25 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
     const int s0 = P->start.s0, l0 = L - s0;
     if (ev) BF_HIP(hipEventRecord(ev[0], P->stream));
     if (s0 == 0)
-        launch_leaf(c, f, P->tk, P->rho, P->buf[0]);
+        launch_leaf(c, f, P->tk, P->rho, B[0]);
     else
-        launch_direct(c, P->start, f, P->tx, P->tk, P->N, P->buf[0]);
+        launch_direct(c, P->start, f, P->tx, P->tk, P->N, B[0]);
     if (ev) BF_HIP(hipEventRecord(ev[1], P->stream));
     if (probe_level == l0)
-        launch_export(c, P->buf[0], P->tx.keys[s0], P->tx.count[s0], P->tk.keys[l0], P->tk.count[l0], l0, L,
+        launch_export(c, B[0], P->tx.keys[s0], P->tx.count[s0], P->tk.keys[l0], P->tk.count[l0], l0, L,
                       P->N, pot);
     if (ev)  // levels above the start have no translation: zero-length intervals
         for (int l = L - 1; l >= l0; --l) BF_HIP(hipEventRecord(ev[2 + (L - 1 - l)], P->stream));
     int cur = 0;
     for (int l = l0 - 1; l >= 0; --l) {
-        launch_translate(c, level_args(P, l, P->buf[cur], P->buf[cur ^ 1]));
+        launch_translate(c, level_args(P, l, B[cur], B[cur ^ 1]));
         if (ev) BF_HIP(hipEventRecord(ev[2 + (L - 1 - l)], P->stream));
         cur ^= 1;
         if (probe_level == l)
-            launch_export(c, P->buf[cur], P->tx.keys[L - l], P->tx.count[L - l], P->tk.keys[l],
+            launch_export(c, B[cur], P->tx.keys[L - l], P->tx.count[L - l], P->tk.keys[l],
                           P->tk.count[l], l, L, P->N, pot);
     }
-    launch_final(c, P->buf[cur], P->tx, P->rho, P->nx, u);
+    launch_final(c, B[cur], P->tx, P->rho, P->nx, u);
     if (ev) BF_HIP(hipEventRecord(ev[L + 2], P->stream));
 }
 
@@ -368,8 +425,9 @@ void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes, const 
 
 void build_tiles(bfsft_plan *P, int lds_bytes)
 {
-    // untuned: the VALU kernel unless BFSFT_TRANSLATE=mfma asks for the other
-    const int kind = kernel_choices(P) == 2 ? 1 : 0;
+    // untuned: the VALU kernel unless the precision or BFSFT_TRANSLATE asks
+    // for another
+    const int kind = first_kind(kernel_choices(P));
     build_tiles_levels(P, std::vector<int>(P->L, lds_bytes), std::vector<int>(P->L, kind));
 }
 
@@ -419,7 +477,7 @@ int choose_start(const bfsft_plan *P)
 void build_plan(bfsft_plan *P, const double *x, const double *k)
 {
     hipStream_t s = P->stream;
-    if (validate_points(x, P->nx, P->d, P->N, s) || validate_points(k, P->nk, P->d, P->N, s))
+    if (validate_points(x, P->nx, P->d, P->N, P->arena, s) || validate_points(k, P->nk, P->d, P->N, P->arena, s))
         throw Error{BFSFT_EDOMAIN, "a coordinate is not finite or lies outside [0, N]"};
     build_tree(P->tx, x, P->nx, P->d, P->L, P->N, P->arena, s);
     build_tree(P->tk, k, P->nk, P->d, P->L, P->N, P->arena, s);
@@ -458,7 +516,11 @@ void release_plan(bfsft_plan *P)
 
 // The adjoint of a single plan: the same trees with the roles of x and k
 // exchanged (T_X of the adjoint is P's T_K and vice versa) and the same
-// tables; its own sigma tables, tiles, state buffers and input staging.
+// tables; its own sigma tables, tiles, start level and input staging.  Its
+// pairs at level l are P's pairs at level L - l, so its largest level has
+// P's size: it shares P's two state buffers (executes on one plan are
+// stream-ordered, never concurrent).  Built with the plan, so no execute
+// call allocates.
 bfsft_plan *make_adjoint(bfsft_plan *P)
 {
     bfsft_plan *A = new bfsft_plan();
@@ -476,9 +538,9 @@ bfsft_plan *make_adjoint(bfsft_plan *P)
                     A->sig[m] = (double *)A->arena.alloc(sizeof(double) * 2 * A->d * A->tx.count[m]);
                     launch_sigma(A->tx.keys[m], A->tx.count[m], A->d, m, A->L, A->N, A->sig[m], A->stream);
                 }
-            const size_t bytes = state_bytes(A);
-            A->buf[0] = A->arena.alloc(bytes);
-            A->buf[1] = A->arena.alloc(bytes);
+            if (state_bytes(A) > state_bytes(P)) throw Error{BFSFT_EDEVICE, "adjoint state larger than the plan's"};
+            A->buf[0] = P->buf[0];
+            A->buf[1] = P->buf[1];
             build_start(A->start, A->tk, choose_start(A), A->d, A->p - 1, A->rho, A->arena, A->stream);
         }
         build_tiles(A, translate_default_lds());
@@ -591,6 +653,7 @@ int bfsft_plan_create(bfsft_plan **out, int d, int64_t N, int p, int precision, 
         init_plan(P, d, N, p, precision, nx, nk, (hipStream_t)stream);
         build_plan(P, x, k);
         if (nx > 0 && nk > 0 && autotune_enabled()) autotune_single(P);
+        P->adj = make_adjoint(P);
         BF_HIP(hipStreamSynchronize(P->stream));
     });
     if (rc != BFSFT_OK) {
@@ -625,8 +688,8 @@ int bfsft_execute_adjoint(bfsft_plan *plan, const double *g, double *v)
         if (plan->nx > 0 && plan->nk > 0 && (const void *)g == (const void *)v)
             throw Error{BFSFT_EINVAL, "v aliases g"};
         if (plan->nk == 0) return;
-        if (!plan->adj) plan->adj = make_adjoint(plan);
-        bfsft_plan *A = plan->adj;
+        bfsft_plan *A = plan->adj;  // built with the plan
+        if (!A) throw Error{BFSFT_EINVAL, "plan has no adjoint"};
         launch_conj(g, A->adj_in, plan->nx, plan->stream);
         run(A, A->adj_in, v, -1, nullptr);
         launch_conj(v, v, plan->nk, plan->stream);
@@ -708,7 +771,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         o->nk = P->nk;
         o->rho = P->rho;
         o->transforms = 1;
-        o->device_bytes = P->arena.bytes;
+        o->device_bytes = P->arena.bytes + (P->adj ? P->adj->arena.bytes : 0);
         o->lds_kb = P->lds / 1024;
         o->start_level = P->start.s0;
         for (int l = 0; l < P->L && l < (int)P->kind.size(); ++l) {

@@ -9,6 +9,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -180,7 +181,25 @@ double time_steps(bfsft_plan *B, int reps)
 
 const char *prec_name(int precision)
 {
-    return precision == BFSFT_FP64 ? "fp64" : precision == BFSFT_MIXED ? "mixed" : "fp32";
+    switch (precision) {
+    case BFSFT_FP64: return "fp64";
+    case BFSFT_FP32: return "fp32";
+    case BFSFT_FP16X2: return "fp16x2";
+    case BFSFT_BF16X3: return "bf16x3";
+    default: return "mixed";
+    }
+}
+
+// BFSFT_BATCHED_WG: forced persistent work-groups per CU (0 = one work-group
+// per item), or -1 when unset
+int batched_wg_env()
+{
+    const char *e = std::getenv("BFSFT_BATCHED_WG");
+    if (!e || !*e) return -1;
+    char *end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    if (end == e || v < 0 || v > 32) return -1;
+    return (int)v;
 }
 
 }  // namespace
@@ -216,12 +235,18 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
         throw Error{BFSFT_ENOMEM, "BFSFT_MAX_DEVICE_BYTES exceeded by the batched plan"};
 
     // autotuning: tile LDS budget x persistent work-groups per CU, timed on
-    // the plan's own steps (results do not depend on either)
+    // the plan's own steps (results do not depend on either);
+    // BFSFT_BATCHED_WG=n forces the launch form (0: one work-group per item,
+    // n > 0: n persistent work-groups per CU) and tunes only the budget
+    const int forced_wg = batched_wg_env();
+    std::vector<int> wg_cand = {0, 4, 5, 8};
+    if (forced_wg >= 0) wg_cand = {forced_wg};
     const std::string key = "batched3/d" + std::to_string(B->d) + "/p" + std::to_string(B->p) + "/" +
-                            prec_name(B->precision) + "/n" + std::to_string(count);
+                            prec_name(B->precision) + "/n" + std::to_string(count) +
+                            (forced_wg >= 0 ? "/w" + std::to_string(forced_wg) : std::string());
     std::vector<int> best;
     if (!tune_lookup(key, best) || best.size() != 2) {
-        best = {32, 4};
+        best = {32, forced_wg >= 0 ? forced_wg : 4};
         if (autotune_enabled()) {
             double best_ms = 1e30;
             // one plain execute per transform (zero sources) leaves finite
@@ -232,7 +257,7 @@ void create_batched(bfsft_plan *B, int count, const bfsft_problem *probs)
             for (int kb : {16, 20, 24, 28, 32, 36, 40}) {
                 for (bfsft_plan *S : B->subs) build_tiles(S, kb * 1024);
                 build_steps(B);
-                for (int wg : {0, 4, 5, 8}) {  // 0: one work-group per item
+                for (int wg : wg_cand) {  // 0: one work-group per item
                     B->grid = ncu * wg;
                     const double ms = time_steps(B, 2);
                     if (ms < best_ms) {

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "bfsft.h"
@@ -34,9 +35,24 @@ void set_last_error(const std::string &m);
 struct Arena {
     std::vector<void *> ptrs;
     int64_t bytes = 0;
-    int64_t cap = -1;  // -1: no cap
+    int64_t temp_bytes = 0;  // live plan-time temporaries (TempList), also under the cap
+    int64_t cap = -1;        // -1: no cap
     void *alloc(size_t n);
     void release();
+    // plan-time temporaries: counted against the cap while alive
+    void *alloc_temp(size_t n);
+    void free_temp(void *p, size_t n);
+};
+
+// Temporaries of one plan-time step, freed when the list goes out of scope.
+struct TempList {
+    Arena &arena;
+    std::vector<std::pair<void *, size_t>> p;
+    explicit TempList(Arena &a) : arena(a) {}
+    TempList(const TempList &) = delete;
+    TempList &operator=(const TempList &) = delete;
+    void *alloc(size_t n);
+    ~TempList();
 };
 
 // -------------------------------------------------------------- tree ------
@@ -60,10 +76,10 @@ struct Tree {
 void build_tree(Tree &t, const double *pts_dev, int64_t n, int d, int L, int64_t N,
                 Arena &arena, hipStream_t s);
 
-// device scan used by the tree build (exclusive, uint32); returns nothing,
-// temporary storage from `arena_tmp`
-void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s,
-                        std::vector<void *> &tmp);
+// device scan used by the tree build (exclusive, uint32); temporary storage
+// from `tmp`
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s, TempList &tmp);
+int validate_points(const double *pts, int64_t n, int d, int64_t N, Arena &arena, hipStream_t s);
 
 // ------------------------------------------------------------- kernels ----
 // Operator tables of one leaf width rho (Section 2.1, as interpolation rows).
@@ -101,7 +117,8 @@ struct LevelArgs {
     int ntile;
     int cost_max;            // most LDS blocks any tile needs (translate_tile_cost)
     int rows;                // rows a' per work-group
-    int kind;                // 0: VALU kernel, 1: matrix-core kernel (2D)
+    int kind;                // 0: VALU kernel, 1: FP64 matrix-core kernel (2D), 2: stage 1 on
+                             //   the matrix cores in the precision's contraction format (2D)
     int64_t nap;             // rows a'
     const double *sig;       // [nap][d] complex exp(2 pi i rho i_{A'}) or null (rho == 1)
 };
@@ -190,6 +207,15 @@ DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, co
                        const Tables &tb, void *state);
 int64_t direct_items(int d, int p, const DirectDesc &dd);
 void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t *prefix, int n, int64_t total);
+
+// 2D translation with stage 1 on the matrix cores in the FP32, FP16X2 or
+// BF16X3 contraction format (FP32 state); kind 2 of a level
+bool translate_xdl_supported(int d, int p, int precision);
+void launch_translate_xdl(const Launch &c, const LevelArgs &la);
+void launch_translate_batched_xdl(const Launch &c, const void *descs, const int64_t *prefix, int ndesc,
+                                  int64_t total, size_t lds, int grid, unsigned long long *next);
+// split-precision formats (stage 1 on the matrix cores only)
+inline bool split_precision(int precision) { return precision == BFSFT_FP16X2 || precision == BFSFT_BF16X3; }
 
 // matrix-core (MFMA) 2D translation with FP64 arithmetic (mixed and FP64)
 bool translate_mfma_supported(int d, int p, int precision);

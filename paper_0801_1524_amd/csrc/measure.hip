@@ -1,0 +1,91 @@
+// Measurement helper: the streaming bandwidth a plain read-and-write kernel
+// reaches on this GPU, at a given element size.  It is the practical memory
+// ceiling the translation kernels are compared with (they read each level's
+// state once and write the next level's once, with the same element sizes).
+#include "bfsft_impl.h"
+
+#include <algorithm>
+
+namespace bfsft {
+
+namespace {
+
+// dst[i] = src[i] over n elements, grid-stride, one element per thread and
+// iteration (the translation's state accesses are of the same width)
+template <typename T>
+__global__ __launch_bounds__(256) void k_stream_copy(const T *__restrict__ src, T *__restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+template <typename T> void launch_copy(const void *src, void *dst, int64_t bytes, unsigned grid, hipStream_t s)
+{
+    k_stream_copy<T><<<grid, 256, 0, s>>>((const T *)src, (T *)dst, bytes / (int64_t)sizeof(T));
+}
+
+}  // namespace
+
+}  // namespace bfsft
+
+using namespace bfsft;
+
+extern "C" int bfsft_copy_rate(int elem_bytes, int64_t bytes, int reps, void *stream, double *gbps)
+{
+    if (!gbps || reps < 1 || bytes < (1 << 20) || bytes > ((int64_t)1 << 34) ||
+        (elem_bytes != 4 && elem_bytes != 8 && elem_bytes != 16) || bytes % elem_bytes) {
+        set_last_error("bfsft_copy_rate: elem_bytes must be 4, 8 or 16, bytes a multiple of it in "
+                       "[2^20, 2^34], reps >= 1, gbps not NULL");
+        return BFSFT_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = BFSFT_OK;
+    auto fail = [&](hipError_t e, int status) {
+        set_last_error(std::string("bfsft_copy_rate: ") + hipGetErrorString(e));
+        rc = status;
+    };
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e != hipSuccess) {
+        fail(e, BFSFT_ENOMEM);
+    } else {
+        int dev = 0, ncu = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ncu = prop.multiProcessorCount;
+        const int64_t n = bytes / elem_bytes;
+        // enough work-groups to fill the chip several times, each thread a few elements
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)ncu * 64);
+        auto launch = [&] {
+            if (elem_bytes == 4) launch_copy<float>(a, b, bytes, grid, s);
+            else if (elem_bytes == 8) launch_copy<float2>(a, b, bytes, grid, s);
+            else launch_copy<float4>(a, b, bytes, grid, s);
+        };
+        e = hipMemsetAsync(a, 0, bytes, s);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) {
+            launch();  // untimed
+            e = hipEventRecord(e0, s);
+        }
+        if (e == hipSuccess) {
+            for (int r = 0; r < reps; ++r) launch();
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess)
+            fail(e, BFSFT_EDEVICE);
+        else
+            *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return rc;
+}

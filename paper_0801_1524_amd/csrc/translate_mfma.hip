@@ -374,7 +374,7 @@ template <typename F> void dispatch_p59(int p, F &&f)
 
 bool translate_mfma_supported(int d, int p, int precision)
 {
-    return d == 2 && p >= 5 && p <= 9 && precision != BFSFT_FP32;
+    return d == 2 && p >= 5 && p <= 9 && (precision == BFSFT_FP64 || precision == BFSFT_MIXED);
 }
 
 size_t translate_mfma_table_doubles(int p) { return (size_t)MShape(p).size; }

@@ -257,25 +257,9 @@ uint32_t read_count(const uint32_t *flags, const uint32_t *pos, int n, hipStream
     return a + b;
 }
 
-struct TmpList {
-    std::vector<void *> p;
-    void *alloc(size_t n)
-    {
-        void *q = nullptr;
-        BF_HIP(hipMalloc(&q, n > 0 ? n : 16));
-        p.push_back(q);
-        return q;
-    }
-    ~TmpList()
-    {
-        for (void *q : p) (void)hipFree(q);
-    }
-};
-
 }  // namespace
 
-void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s,
-                        std::vector<void *> &tmp)
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s, TempList &tmp)
 {
     if (n <= 0) return;
     const int nt = nblk(n, kTile);
@@ -284,11 +268,8 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s,
         BF_HIP(hipGetLastError());
         return;
     }
-    uint32_t *sums = nullptr, *sums_scan = nullptr;
-    BF_HIP(hipMalloc(&sums, sizeof(uint32_t) * nt));
-    tmp.push_back(sums);
-    BF_HIP(hipMalloc(&sums_scan, sizeof(uint32_t) * nt));
-    tmp.push_back(sums_scan);
+    uint32_t *sums = (uint32_t *)tmp.alloc(sizeof(uint32_t) * nt);
+    uint32_t *sums_scan = (uint32_t *)tmp.alloc(sizeof(uint32_t) * nt);
     k_scan_tiles<<<nt, kThreads, 0, s>>>(in, out, n, sums);
     BF_HIP(hipGetLastError());
     scan_exclusive_u32(sums, sums_scan, nt, s, tmp);
@@ -296,10 +277,10 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n, hipStream_t s,
     BF_HIP(hipGetLastError());
 }
 
-int validate_points(const double *pts, int64_t n, int d, int64_t N, hipStream_t s)
+int validate_points(const double *pts, int64_t n, int d, int64_t N, Arena &arena, hipStream_t s)
 {
     if (n == 0) return 0;
-    TmpList tmp;
+    TempList tmp(arena);
     int *bad = (int *)tmp.alloc(sizeof(int));
     int zero = 0, host = 0;
     BF_HIP(hipMemcpyAsync(bad, &zero, sizeof(int), hipMemcpyHostToDevice, s));
@@ -324,7 +305,7 @@ void build_tree(Tree &t, const double *pts, int64_t n64, int d, int L, int64_t N
     if (n64 == 0) return;
     const int n = (int)n64;
 
-    TmpList tmp;
+    TempList tmp(arena);
     uint64_t *ka = (uint64_t *)tmp.alloc(sizeof(uint64_t) * n);
     uint64_t *kb = (uint64_t *)tmp.alloc(sizeof(uint64_t) * n);
     int32_t *vb = (int32_t *)tmp.alloc(sizeof(int32_t) * n);
@@ -341,7 +322,7 @@ void build_tree(Tree &t, const double *pts, int64_t n64, int d, int L, int64_t N
     const int ntiles = nblk(n, kTile);
     uint32_t *hist = (uint32_t *)tmp.alloc(sizeof(uint32_t) * 256 * ntiles);
     uint32_t *offs = (uint32_t *)tmp.alloc(sizeof(uint32_t) * 256 * ntiles);
-    std::vector<void *> &scan_tmp = tmp.p;
+    TempList &scan_tmp = tmp;
     for (int shift = 0; shift < d * L; shift += 8) {
         k_rs_hist<<<ntiles, kThreads, 0, s>>>(ka, n, shift, hist, ntiles);
         BF_HIP(hipGetLastError());

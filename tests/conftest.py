@@ -1,3 +1,4 @@
+import json
 import os
 import sys
 
@@ -33,3 +34,15 @@ def rel_l2(a, b):
     b = np.asarray(b)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def within_measured(err, measured, name, factor=3.0):
+    """Assert err <= factor x the deviation measured on the GPU for this case
+    (reduced-precision paths against the oracle); with BFSFT_ERR_LOG set,
+    also append the case and its error to that file (for refreshing the
+    measured values)."""
+    path = os.environ.get("BFSFT_ERR_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps({"case": name, "err": err, "measured": measured}) + "\n")
+    assert err <= factor * measured, f"{name}: {err:.3e} > {factor} x measured {measured:.3e}"

@@ -52,6 +52,10 @@ def test_strerror_and_destroy_null(lib):
     (3, 256, 8, 0),      # 3D p = 8 at FP64: one box and its children exceed the LDS
     (2, 1, 5, 0),        # N < 2
     (2, 256, 5, 7),      # unknown precision
+    (2, 256, 5, 5),
+    (2, 256, 5, -1),
+    (3, 256, 5, 2),      # the split contraction formats are 2D only
+    (3, 256, 5, 3),
 ])
 def test_invalid_scalars_rejected_on_host(lib, d, N, p, prec):
     h = ctypes.c_void_p(1234)
@@ -80,3 +84,15 @@ def test_batched_without_problems_rejected(lib):
     assert lib.bfsft_plan_create_batched(ctypes.byref(h), 3, None, 2, 5, 0, None) == -1
     assert lib.bfsft_last_error()
     assert lib.bfsft_execute_adjoint(None, None, None) == -1
+
+
+def test_precision_values_match_the_boundary():
+    """The precision codes of the header: FP64 = 0, FP32 = 1, FP16X2 = 2,
+    BF16X3 = 3, MIXED = 4; the binding uses the same values."""
+    import paper_0801_1524_amd as bf
+    text = open(HEADER).read()
+    vals = dict(re.findall(r"#define (BFSFT_(?:FP64|FP32|FP16X2|BF16X3|MIXED))\s+(\d+)", text))
+    assert vals == {"BFSFT_FP64": "0", "BFSFT_FP32": "1", "BFSFT_FP16X2": "2", "BFSFT_BF16X3": "3",
+                    "BFSFT_MIXED": "4"}
+    for name, code in bf.PRECISIONS.items():
+        assert vals["BFSFT_" + name.upper()] == str(code)

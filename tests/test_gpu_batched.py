@@ -5,7 +5,7 @@ oracle; graph replays interleaved with other eager work must all agree."""
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import rel_l2, within_measured
 from paper_0801_1524_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -37,26 +37,48 @@ def split(u, probs):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
-def test_batched_equals_serial_and_oracle(bf, oracle_mod, precision):
+# largest rel-l2 vs O2 over the seven transforms of small_batch(), measured
+# on an MI355X (both launch forms); the bar is 3x
+MEASURED_BATCH = {"mixed": 1.66e-7, "fp32": 8.24e-7}
+
+
+@pytest.fixture(scope="module")
+def batch_oracle(oracle_mod):
     probs = small_batch()
-    with_n = [(q.N, q.x, q.k) for q in probs]
-    B = bf.BatchedPlan(with_n, 2, 7, precision)
+    return probs, [oracle_mod.Butterfly(2, q.N, q.p, q.x, q.k).run(q.f) for q in probs]
+
+
+@pytest.mark.parametrize("wg", ["0", "4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
+def test_batched_equals_serial_and_oracle(bf, batch_oracle, monkeypatch, precision, wg):
+    """Both launch forms of a sweep step, forced: one work-group per work
+    item (wg = 0) and 4 persistent work-groups per CU taking items from a
+    counter (wg = 4)."""
+    monkeypatch.setenv("BFSFT_BATCHED_WG", wg)
+    probs, ubs = batch_oracle
+    B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, precision)
+    assert B.info()["wg_per_cu"] == int(wg)
     f = packed(probs)
     ug = B.execute(f).cpu().numpy()
     us = B.execute(f, serial=True).cpu().numpy()
     B.close()
     assert rel_l2(ug, us) <= 1e-14
-    tol = {"fp64": 1e-10, "mixed": 2e-6, "fp32": 3e-5}[precision]
-    for q, u in zip(probs, split(ug, probs)):
-        ub = oracle_mod.Butterfly(2, q.N, q.p, q.x, q.k).run(q.f)
-        assert rel_l2(u, ub) <= tol, (q.name, q.N)
+    worst = max(rel_l2(u, ub) for u, ub in zip(split(ug, probs), ubs))
+    if precision == "fp64":
+        assert worst <= 1e-10
+    else:
+        within_measured(worst, MEASURED_BATCH[precision], f"batched wg={wg} {precision}")
 
 
-def test_graph_replays_agree(bf):
+@pytest.mark.parametrize("wg", ["0", "4"])
+def test_graph_replays_agree(bf, monkeypatch, wg):
+    """Replays of the graph (the persistent form zeroes its item counters
+    inside the graph with a kernel) agree bit for bit."""
     import torch
+    monkeypatch.setenv("BFSFT_BATCHED_WG", wg)
     probs = small_batch(count=5, seed=3)
     B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, "mixed")
+    assert B.info()["wg_per_cu"] == int(wg)
     f = torch.from_numpy(packed(probs)).to("cuda")
     first = B.execute(f).cpu().numpy()
     for i in range(4):
@@ -91,8 +113,10 @@ def test_batched_single_and_all_empty(bf):
 
 
 def test_batched_chunked_launches(bf, monkeypatch):
-    """The batched step launches split into chunks of 7 work-groups give the
-    same bits as single launches (same tuned choices, read from the cache)."""
+    """The batched step launches (one work-group per item, forced) split into
+    chunks of 7 work-groups give the same bits as single launches (same tuned
+    choices, read from the cache)."""
+    monkeypatch.setenv("BFSFT_BATCHED_WG", "0")
     probs = small_batch(count=4, seed=13)
     f = packed(probs)
     monkeypatch.delenv("BFSFT_MAX_GROUPS", raising=False)
@@ -152,4 +176,5 @@ def test_c4_full_size_sampled(bf, oracle_mod):
         ud = oracle_mod.direct(q.x, q.k, q.f, q.N, S)
         num += np.sum(np.abs(uu[S] - ud) ** 2)
         den += np.sum(np.abs(ud) ** 2)
-    assert np.sqrt(num / den) <= 3e-4
+    # measured 2.6e-6 (p = 7: the method's own error, about 1e-5 in Table 1)
+    within_measured(float(np.sqrt(num / den)), 2.6e-6, "c4 sampled vs direct sum")

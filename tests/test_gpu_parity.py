@@ -5,20 +5,31 @@ Bars (each written in its test):
   and on the check potentials of every probed level (same conventions, so
   the two differ only by rounding).
 * every precision vs the direct sum O1 at the method's accuracy for p.
-* "mixed" (FP32 state, FP64 arithmetic): vs O2 within 2e-6; "fp32" within
-  3e-5 (the FP32 rounding of the state and of the arithmetic, measured
-  budget at p <= 9).
+* "mixed" (FP32 state, FP64 arithmetic) and "fp32" (FP32 state and
+  arithmetic) vs O2: within 3x the deviation measured on an MI355X for the
+  same case (their rounding only), so a tenfold accuracy loss fails.
 """
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import rel_l2, within_measured
 from paper_0801_1524_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 EPS = {3: 0.5, 4: 0.05, 5: 6e-3, 6: 1e-3, 7: 3e-4, 8: 2e-5, 9: 1.5e-6, 10: 2e-7, 11: 5e-8, 12: 1e-8}
-TOL_O2 = {"fp64": 1e-10, "mixed": 2e-6, "fp32": 3e-5}
+# rel-l2 vs O2 measured on an MI355X (the bar is 3x these; FP64 is held to 1e-10)
+MEASURED_O2 = {("c0", "mixed"): 9.57e-8, ("c0", "fp32"): 4.72e-7,
+               ("c1", "mixed"): 1.66e-7, ("c1", "fp32"): 4.35e-7,
+               ("sph16p7", "mixed"): 1.5e-7, ("sph24p8", "mixed"): 2.3e-7, ("sph16p8", "fp32"): 6.0e-7,
+               ("sph32p5", "mixed"): 1.0e-7, ("sph32p5", "fp32"): 3.9e-7}
+
+
+def check_o2(err, case, precision):
+    if precision == "fp64":
+        assert err <= 1e-10, (case, err)
+    else:
+        within_measured(err, MEASURED_O2[(case, precision)], f"{case} {precision}")
 
 
 @pytest.fixture(scope="module")
@@ -45,7 +56,7 @@ def test_configs_vs_oracle(bf, oracle_mod, name, precision):
     P = synth.config(name)
     u = gpu_u(bf, P, precision)
     ub = oracle_u(oracle_mod, P)
-    assert rel_l2(u, ub) <= TOL_O2[precision]
+    check_o2(rel_l2(u, ub), name, precision)
     S = synth.error_subset(P.nx, synth.CONFIG_NAMES.index(name))
     assert rel_l2(u[S], oracle_mod.direct(P.x, P.k, P.f, P.N, S)) <= EPS[P.p]
 
@@ -275,7 +286,7 @@ def test_3d_large_p_both_lds_layouts(bf, oracle_mod, N, p, precision):
     k = synth.sphere(N, radius=0.3)
     f = synth.gaussian_sources(k.shape[0], N + p)
     P = synth.Problem("sphp", 3, N, p, x, k, f)
-    assert rel_l2(gpu_u(bf, P, precision), oracle_u(oracle_mod, P)) <= TOL_O2[precision]
+    check_o2(rel_l2(gpu_u(bf, P, precision), oracle_u(oracle_mod, P)), f"sph{N}p{p}", precision)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
@@ -286,7 +297,7 @@ def test_3d_sphere_vs_oracle_and_direct(bf, oracle_mod, precision):
     f = synth.gaussian_sources(k.shape[0], 3)
     P = synth.Problem("sph32", 3, N, p, x, k, f)
     u = gpu_u(bf, P, precision)
-    assert rel_l2(u, oracle_u(oracle_mod, P)) <= TOL_O2[precision]
+    check_o2(rel_l2(u, oracle_u(oracle_mod, P)), "sph32p5", precision)
     assert rel_l2(u, oracle_mod.direct(x, k, f, N)) <= EPS[p]
 
 
@@ -336,3 +347,30 @@ def test_c3_full_size_vs_oracle_sampled_targets(bf, oracle_mod, c3):
     u = gpu_u(bf, c3, "fp64")
     ub = oracle_mod.Butterfly(c3.d, c3.N, c3.p, c3.x[S], c3.k).run(c3.f)
     assert rel_l2(u[S], ub) <= 1e-10
+
+
+def test_binding_checks_and_stream_order(bf, oracle_mod):
+    """The binding rejects a source vector of the wrong length and output
+    tensors it cannot write; an execute issued while another stream is
+    current is ordered with it (same result as on the plan's stream)."""
+    import torch
+    P = synth.config("c0")
+    with bf.Plan(P.d, P.N, P.p, P.x, P.k, "fp64") as plan:
+        ref = plan.execute(P.f).cpu().numpy()
+        with pytest.raises(ValueError):
+            plan.execute(P.f[:-1])
+        with pytest.raises(ValueError):
+            plan.execute(P.f, out=torch.empty(P.nx - 1, dtype=torch.complex128, device="cuda"))
+        with pytest.raises(ValueError):
+            plan.execute(P.f, out=torch.empty(P.nx, dtype=torch.complex64, device="cuda"))
+        with pytest.raises(ValueError):
+            plan.execute(P.f, out=torch.empty(2 * P.nx, dtype=torch.complex128, device="cuda")[::2])
+        with pytest.raises(ValueError):
+            plan.execute_adjoint(np.zeros(P.nx + 1, complex))
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            f = torch.from_numpy(P.f).to("cuda")
+            u = plan.execute(f * 1.0)
+            got = u.cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert rel_l2(ref, oracle_u(oracle_mod, P)) <= 1e-10
