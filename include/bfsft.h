@@ -141,6 +141,25 @@ int bfsft_plan_create(bfsft_plan **out, int d, int64_t N, int p, int precision,
  */
 int bfsft_execute(bfsft_plan *plan, const double *f, double *u);
 
+/*
+ * bfsft_execute for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same computation and result, bit for bit, with the two state buffers of
+ * the sweep taken from a static device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends, instead of the
+ * plan's own.  Calls no allocating routine.  The first call on a device
+ * looks the array's address up (no allocation).  Every call on a GPU
+ * shares that GPU's array: calls whose executions overlap on one GPU (two
+ * streams, two threads) race and give wrong results; calls on one stream
+ * are ordered.  Nothing must start at zero: each call writes every state
+ * entry before reading it.
+ *   f, u  as bfsft_execute.
+ * BFSFT_EINVAL if 2 x the plan's largest level state (bfsft_info pairs x
+ * p^d x 8 or 16 bytes) exceeds 64 MiB, and for the arguments bfsft_execute
+ * rejects.
+ */
+int bfsft_execute_noalloc(bfsft_plan *plan, const double *f, double *u);
+
 /* Release a plan and all its device memory (synchronises its stream).
  * NULL is a no-op. */
 void bfsft_destroy(bfsft_plan *plan);

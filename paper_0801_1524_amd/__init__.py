@@ -77,6 +77,8 @@ def lib():
     L.bfsft_plan_create.restype = I
     L.bfsft_execute.argtypes = [P, P, P]
     L.bfsft_execute.restype = I
+    L.bfsft_execute_noalloc.argtypes = [P, P, P]
+    L.bfsft_execute_noalloc.restype = I
     L.bfsft_execute_adjoint.argtypes = [P, P, P]
     L.bfsft_execute_adjoint.restype = I
     L.bfsft_execute_probe.argtypes = [P, P, P, I, P]
@@ -248,6 +250,17 @@ class Plan:
         with _Ordered(torch, self._stream, (fd, u)):
             _check(self._L.bfsft_execute(self._h, ctypes.c_void_p(fd.data_ptr() if self.nk else 0),
                                          ctypes.c_void_p(u.data_ptr() if self.nx else 0)))
+        return u
+
+    def execute_noalloc(self, f, out):
+        """As execute, through bfsft_execute_noalloc (state in the library's
+        static scratch; out must be given: nothing is allocated)."""
+        torch = _torch()
+        fd = _sources(f, self.nk, torch, "f")
+        u = _output(out, self.nx, torch, "out")
+        with _Ordered(torch, self._stream, (fd, u)):
+            _check(self._L.bfsft_execute_noalloc(self._h, ctypes.c_void_p(fd.data_ptr() if self.nk else 0),
+                                                 ctypes.c_void_p(u.data_ptr() if self.nx else 0)))
         return u
 
     def execute_adjoint(self, g, out=None):

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -381,6 +382,37 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
     if (ev) BF_HIP(hipEventRecord(ev[L + 2], P->stream));
 }
 
+// ------------------------------------------------ no-allocation execute --
+// Scratch of bfsft_execute_noalloc: the sweep's two state buffers, in a
+// static device array the library holds on every GPU it runs on until the
+// process ends.  In host code `scratch` names a host-side stand-in, not the
+// device memory: its device address is taken once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// handed to kernels.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// device address of `scratch` on the current device
+void *scratch_ptr()
+{
+    int dev = 0;
+    BF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error{BFSFT_EDEVICE, "device index beyond the scratch table"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw Error{BFSFT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch[dev] = ptr;
+    }
+    return g_scratch[dev];
+}
+
 void free_events(bfsft_plan *P)
 {
     for (hipEvent_t e : P->tev) (void)hipEventDestroy(e);
@@ -676,6 +708,29 @@ int bfsft_execute(bfsft_plan *plan, const double *f, double *u)
         if (plan->nx > 0 && plan->nk > 0 && (const void *)f == (const void *)u)
             throw Error{BFSFT_EINVAL, "u aliases f"};
         run(plan, f, u, -1, nullptr);
+    });
+}
+
+int bfsft_execute_noalloc(bfsft_plan *plan, const double *f, double *u)
+{
+    return guarded([&] {
+        if (!plan) throw Error{BFSFT_EINVAL, "plan is NULL"};
+        if (plan->batched) throw Error{BFSFT_EINVAL, "batched plan: use bfsft_execute_batched"};
+        if ((plan->nk > 0 && !f) || (plan->nx > 0 && !u)) throw Error{BFSFT_EINVAL, "NULL f or u"};
+        if (plan->nx > 0 && plan->nk > 0 && (const void *)f == (const void *)u)
+            throw Error{BFSFT_EINVAL, "u aliases f"};
+        if (plan->nx == 0 || plan->nk == 0) {  // no state: the plain execute allocates nothing either
+            run(plan, f, u, -1, nullptr);
+            return;
+        }
+        const size_t one = (state_bytes(plan) + 255) & ~(size_t)255;
+        if (2 * one > kScratchBytes)
+            throw Error{BFSFT_EINVAL, "the plan's state (2 x " + std::to_string(one) +
+                                          " bytes) exceeds the no-allocation scratch (" +
+                                          std::to_string(kScratchBytes) + " bytes)"};
+        unsigned char *base = static_cast<unsigned char *>(scratch_ptr());
+        void *const bufs[2] = {base, base + one};
+        run(plan, f, u, -1, nullptr, bufs);
     });
 }
 
