@@ -48,47 +48,58 @@ WORKLOADS = {
 
 
 def bench_batched(args, torch, bf, synth):
-    """c4: batched graph execute vs per-transform plain launches."""
-    probs = synth.batched_config()
-    prec = args.precisions.split(",")[0]
-    t0 = time.perf_counter()
-    B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, 7, prec)
-    t_plan = time.perf_counter() - t0
-    info = B.info()
+    """c4: the batched graph (one launch per sweep step over all transforms)
+    per precision, the first precision's per-transform launches beside it,
+    and every precision's sampled error against the direct sum."""
+    p = args.p or 7
+    probs = synth.batched_config(p=p)
+    precs = args.precisions.split(",")
     f = torch.from_numpy(np.concatenate([q.f for q in probs])).to("cuda")
-    u = torch.empty(B.nx, dtype=torch.complex128, device="cuda")
+    offs = np.cumsum([0] + [q.nx for q in probs])
+    # sampled reference (the accuracy check of the line, a second or so):
+    # every 8th transform, 40 outputs each, direct sum (eq. (1))
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(4)
+    ref = []
+    for t in range(0, len(probs), 8):
+        q = probs[t]
+        S = np.sort(rng.choice(q.nx, 40, replace=False))
+        ref.append((t, S, oracle.direct(q.x, q.k, q.f, q.N, S)))
     res = {}
-    for mode, serial in (("graph", False), ("serial", True)):
-        for _ in range(args.warmup):
-            B.execute(f, out=u, serial=serial)
-        torch.cuda.synchronize()
+    for prec in precs:
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            B.execute(f, out=u, serial=serial)
-        torch.cuda.synchronize()
-        res[mode] = (time.perf_counter() - t0) * 1e3 / args.steps
-        log(f"[bench] c4 {prec} {mode}: {res[mode]:.3f} ms/step")
-    out = u.cpu().numpy()
-    B.close()
-    err = None
+        B = bf.BatchedPlan([(q.N, q.x, q.k) for q in probs], 2, p, prec)
+        t_plan = time.perf_counter() - t0
+        info = B.info()
+        u = torch.empty(B.nx, dtype=torch.complex128, device="cuda")
+        modes = (("graph", False), ("serial", True)) if prec == precs[0] else (("graph", False),)
+        r = {"plan_seconds": round(t_plan, 2), "lds_kb": info["lds_kb"], "wg_per_cu": info["wg_per_cu"]}
+        for mode, serial in modes:
+            for _ in range(args.warmup):
+                B.execute(f, out=u, serial=serial)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                B.execute(f, out=u, serial=serial)
+            torch.cuda.synchronize()
+            r[mode + "_ms"] = (time.perf_counter() - t0) * 1e3 / args.steps
+            log(f"[bench] c4 p={p} {prec} {mode}: {r[mode + '_ms']:.3f} ms/step")
+        out = u.cpu().numpy()
+        if ref:
+            num = den = 0.0
+            for t, S, ud in ref:
+                num += np.sum(np.abs(out[offs[t] + S] - ud) ** 2)
+                den += np.sum(np.abs(ud) ** 2)
+            r["err_rel_l2_sampled"] = float(np.sqrt(num / den))
+            log(f"[bench] c4 p={p} {prec}: sampled rel-l2 vs direct sum {r['err_rel_l2_sampled']:.3e}")
+        r["sweep_bytes"] = info["sweep_bytes"]
+        nx = B.nx
+        B.close()
+        res[prec] = r
     base = None
     if not args.no_cpu:
         import oracle
-        oracle.build(force=False)
-        rng = np.random.default_rng(4)
-        num = den = 0.0
-        off = 0
-        offs = []
-        for q in probs:
-            offs.append(off)
-            off += q.nx
-        for t in range(0, len(probs), 8):
-            q = probs[t]
-            S = np.sort(rng.choice(q.nx, 40, replace=False))
-            ud = oracle.direct(q.x, q.k, q.f, q.N, S)
-            num += np.sum(np.abs(out[offs[t] + S] - ud) ** 2)
-            den += np.sum(np.abs(ud) ** 2)
-        err = float(np.sqrt(num / den))
         # oracle butterfly on a bounded sample: every 16th transform, scaled to outputs/s
         t0 = time.perf_counter()
         nsample = 0
@@ -97,33 +108,41 @@ def bench_batched(args, torch, bf, synth):
             nsample += q.nx
         tb = time.perf_counter() - t0
         base = {"value": round(nsample / tb, 1), "unit": "outputs/s", "cores": oracle.threads(),
-                "kind": "oracle", "sample": f"16 of the 256 transforms ({nsample} outputs)",
-                "seconds": round(tb, 3)}
-    ms = res["graph"]
+                "cpu_model": cpu_model(), "kind": "oracle",
+                "sample": f"16 of the 256 transforms ({nsample} outputs)", "seconds": round(tb, 3)}
+    head = precs[0]
+    ms = res[head]["graph_ms"]
+    wl = WORKLOADS["c4"] if p == 7 else WORKLOADS["c4"].replace("p=7", f"p={p}")
     line = {
         "metric": "outputs u_i/sec (batched uneven-N transforms)",
-        "value": round(B.nx / (ms / 1e3), 1), "unit": "outputs/s", "n_gpus": 1,
+        "value": round(nx / (ms / 1e3), 1), "unit": "outputs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["c4"], "transforms": len(probs), "nx": B.nx, "nk": B.nk,
-                   "precision": prec, "lds_kb": info["lds_kb"], "wg_per_cu": info["wg_per_cu"]},
-        "err_rel_l2_sampled": err,
-        "serial_ms_per_step": round(res["serial"], 4),
-        "speedup_vs_serial": round(res["serial"] / ms, 3),
-        "plan_seconds": round(t_plan, 2),
-        "sweep_bytes": info["sweep_bytes"],
-        "achieved_GBps_whole_step": round(info["sweep_bytes"] / (ms / 1e3) / 1e9, 1),
+        "dtype": DTYPE[head], "data": "synthetic",
+        "config": {"workload": wl, "transforms": len(probs), "nx": nx, "p": p, "precision": head},
+        "err_rel_l2_sampled": res[head].get("err_rel_l2_sampled"),
+        "serial_ms_per_step": round(res[head]["serial_ms"], 4),
+        "speedup_vs_serial": round(res[head]["serial_ms"] / ms, 3),
+        "precisions": {k: {"graph_ms_per_step": round(v["graph_ms"], 4),
+                           "outputs_per_s": round(nx / (v["graph_ms"] / 1e3), 1),
+                           "err_rel_l2_sampled": v.get("err_rel_l2_sampled"),
+                           "achieved_GBps_whole_step": round(v["sweep_bytes"] / (v["graph_ms"] / 1e3) / 1e9, 1),
+                           "plan_seconds": v["plan_seconds"], "lds_kb": v["lds_kb"], "wg_per_cu": v["wg_per_cu"]}
+                       for k, v in res.items()},
         "cpu_baseline": base,
     }
+    if "fp64" in res and head != "fp64":
+        line["speedup_vs_fp64_graph"] = round(res["fp64"]["graph_ms"] / ms, 3)
     print(json.dumps(line), flush=True)
+
+
 GATE = 1e-6
 # arithmetic of each precision's sweep (leaf, phases and evaluation are FP64 in all)
 DTYPE = {"fp64": "f64", "mixed": "f64", "fp32": "f32", "fp16x2": "f16x2", "bf16x3": "bf16x3"}
 COUNTERS = os.path.join(ROOT, "profiles", "translate_c2_counters.json")
 # sources of the translation kernels (the counters are valid while these are unchanged)
 KERNEL_SRC = [os.path.join(ROOT, "paper_0801_1524_amd", "csrc", f)
-              for f in ("translate.hip", "translate_common.h", "cplx.h")]
+              for f in ("translate.hip", "translate2d.h", "translate_xdl.hip", "translate_common.h", "cplx.h")]
 
 
 def log(*a):
@@ -344,7 +363,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precisions", default="mixed,fp64,fp32,fp16x2,bf16x3")
+    ap.add_argument("--precisions", default=None,
+                    help="comma-separated, the first is c4's headline (default: mixed,fp64,fp32,fp16x2,bf16x3; "
+                         "c4: mixed,fp64,bf16x3)")
+    ap.add_argument("--p", type=int, default=None, help="c4 only: p of the batched transforms (default 7)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="FETCH_DIR WRITE_DIR [VALU_DIR]: write the translation kernel's per-launch "
                          "counters from rocprofv3 --pmc runs (FETCH_SIZE; WRITE_SIZE; the VALU "
@@ -359,6 +381,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    if args.precisions is None:
+        args.precisions = "mixed,fp64,bf16x3" if args.workload == "c4" else "mixed,fp64,fp32,fp16x2,bf16x3"
     if args.summarize_counters:
         dirs = list(args.summarize_counters) + [None]
         summarize_counters(dirs[0], dirs[1], dirs[2], args.precisions.split(",")[0], COUNTERS)

@@ -181,6 +181,20 @@ int bfsft_plan_info(const bfsft_plan *plan, bfsft_info *out);
 int bfsft_plan_boxes(const bfsft_plan *plan, int side, int m, int64_t *coords);
 
 /*
+ * The per-axis interpolation tables of a single plan, as built on the device
+ * (FP64), for tests of the operators of Section 2.1 (eqs. (M1), (E1)).  The
+ * state of a box pair is B's check potential at A's check points with B's
+ * corner phase divided out, rotated by E; one level of step 3 applies, per
+ * axis, diag(sigma^s G(s, t, .)) R_t to the state of the child pair
+ * (A', B_s), A = child t of A', sigma = exp(2 pi i rho i_{A'}).
+ *   R  host, [2 t][p l][p l'] real: R_t
+ *   G  host, [2 s][2 t][p l] complex (interleaved): G(s, t, l)
+ *   E  host, [p] complex: E[k] = exp(-i pi rho k / q)
+ * Synchronises the plan stream.
+ */
+int bfsft_plan_tables(const bfsft_plan *plan, double *R, double *G, double *E);
+
+/*
  * Parity probe: run bfsft_execute and also export the check potentials
  * u^{AB}_l = sum over sources of B of exp(2 pi i x^A_l . k / N) f, as
  * reproduced by the sweep at T_K level `level` (Section 2.1: the potentials

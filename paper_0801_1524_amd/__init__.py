@@ -91,6 +91,8 @@ def lib():
     L.bfsft_last_error.restype = ctypes.c_char_p
     L.bfsft_plan_info.argtypes = [P, ctypes.POINTER(Info)]
     L.bfsft_plan_info.restype = I
+    L.bfsft_plan_tables.argtypes = [P, P, P, P]
+    L.bfsft_plan_tables.restype = I
     L.bfsft_plan_boxes.argtypes = [P, I, I, P]
     L.bfsft_plan_boxes.restype = I
     L.bfsft_plan_create_batched.argtypes = [PP, I, ctypes.POINTER(Problem), I, I, I, P]
@@ -306,6 +308,17 @@ class Plan:
         _check(self._L.bfsft_timing_end(self._h, out, 3 + L))
         return {"executes": int(out[0]), "leaf_ms": out[1], "final_ms": out[2],
                 "translate_ms": [out[3 + l] for l in range(L)]}
+
+    def tables(self):
+        """(R, G, E): the device's interpolation tables (bfsft_plan_tables):
+        R (2, p, p) real, G (2 s, 2 t, p) complex, E (p,) complex."""
+        p = self.p
+        R = np.zeros((2, p, p), dtype=np.float64)
+        G = np.zeros((2, 2, p), dtype=np.complex128)
+        E = np.zeros(p, dtype=np.complex128)
+        _check(self._L.bfsft_plan_tables(self._h, R.ctypes.data_as(ctypes.c_void_p),
+                                         G.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p)))
+        return R, G, E
 
     def boxes(self, side: str, m: int) -> np.ndarray:
         info = self.info()

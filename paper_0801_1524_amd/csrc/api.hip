@@ -850,6 +850,18 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
     });
 }
 
+int bfsft_plan_tables(const bfsft_plan *P, double *R, double *G, double *E)
+{
+    return guarded([&] {
+        if (!P || P->batched || !R || !G || !E) throw Error{BFSFT_EINVAL, "NULL argument or batched plan"};
+        const size_t p = (size_t)P->p;
+        BF_HIP(hipMemcpyAsync(R, P->tb.R64, sizeof(double) * 2 * p * p, hipMemcpyDeviceToHost, P->stream));
+        BF_HIP(hipMemcpyAsync(G, P->tb.C64, sizeof(double) * 2 * 4 * p, hipMemcpyDeviceToHost, P->stream));
+        BF_HIP(hipMemcpyAsync(E, P->tb.erot, sizeof(double) * 2 * p, hipMemcpyDeviceToHost, P->stream));
+        BF_HIP(hipStreamSynchronize(P->stream));
+    });
+}
+
 int bfsft_plan_boxes(const bfsft_plan *P, int side, int m, int64_t *coords)
 {
     return guarded([&] {

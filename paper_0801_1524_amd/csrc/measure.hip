@@ -10,13 +10,21 @@ namespace bfsft {
 
 namespace {
 
-// dst[i] = src[i] over n elements, grid-stride, one element per thread and
-// iteration (the translation's state accesses are of the same width)
+// dst[i] = src[i] over n elements of the translation's access width: each
+// work-group copies 4 x 256 consecutive elements, each thread four of them
+// 256 apart (every access instruction of a wave is one contiguous range),
+// with its four loads issued before its stores
 template <typename T>
 __global__ __launch_bounds__(256) void k_stream_copy(const T *__restrict__ src, T *__restrict__ dst, int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    T v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (i0 + 256 * j < n) v[j] = src[i0 + 256 * j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (i0 + 256 * j < n) dst[i0 + 256 * j] = v[j];
 }
 
 template <typename T> void launch_copy(const void *src, void *dst, int64_t bytes, unsigned grid, hipStream_t s)
@@ -51,13 +59,9 @@ extern "C" int bfsft_copy_rate(int elem_bytes, int64_t bytes, int reps, void *st
     if (e != hipSuccess) {
         fail(e, BFSFT_ENOMEM);
     } else {
-        int dev = 0, ncu = 256;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            ncu = prop.multiProcessorCount;
         const int64_t n = bytes / elem_bytes;
-        // enough work-groups to fill the chip several times, each thread a few elements
-        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)ncu * 64);
+        // one work-group per 1024 elements (at most 2^22 of them: 2^34 bytes of 4-byte elements)
+        const unsigned grid = (unsigned)((n + 1023) / 1024);
         auto launch = [&] {
             if (elem_bytes == 4) launch_copy<float>(a, b, bytes, grid, s);
             else if (elem_bytes == 8) launch_copy<float2>(a, b, bytes, grid, s);

@@ -20,9 +20,9 @@
 //           power of two so that its largest part lies in [2^14, 2^15)
 //           (FP16 range), and its results are scaled back exactly;
 //   BF16X3  v_mfma_f32_16x16x16_bf16 on exact three-term splits of the FP32
-//           values (8 + 8 + 8 significant bits, truncation) and of R rounded
-//           to FP32, six products x_a R_b with a + b <= 2; BF16 has the FP32
-//           exponent range, so no scaling.
+//           values (8 + 8 + 8 significant bits, each piece rounded to nearest
+//           even) and of R rounded to FP32, six products x_a R_b with
+//           a + b <= 2; BF16 has the FP32 exponent range, so no scaling.
 //
 // Operand layouts (checked on the GPU with an in-bounds probe): for the
 // 16x16x4 f32 product lane i + 16k holds A[i][k] and B[k][i]; for the
@@ -44,8 +44,11 @@ namespace {
 using namespace tr;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 constexpr int kF32 = 0, kF16X2 = 1, kBF16X3 = 2;
 
@@ -84,8 +87,41 @@ template <int P> struct XOp<P, kBF16X3> {
 };
 
 __device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(x) >> 16); }
-// x truncated to its leading 8 significant bits (a BF16 value, as FP32)
-__device__ __forceinline__ float bf16_trunc(float x) { return __uint_as_float(__float_as_uint(x) & 0xffff0000u); }
+
+// Two FP32 values rounded to BF16 (to nearest even, one v_cvt_pk_bf16_f32),
+// as packed bits and as FP32 values.  Round to nearest keeps the terms a
+// split drops unbiased: truncation makes them all of one sign.
+__device__ __forceinline__ unsigned bf16_pair(float a, float b, float &ra, float &rb)
+{
+    const bf16x2v h = __builtin_convertvector(f32x2{a, b}, bf16x2v);
+    const unsigned u = __builtin_bit_cast(unsigned, h);
+    ra = __uint_as_float(u << 16);
+    rb = __uint_as_float(u & 0xffff0000u);
+    return u;
+}
+
+// Exact three-term splits of two FP32 values into BF16 pieces, packed in
+// pairs: x = x0 + x1 + x2 (x - x0 has at most 16 significant bits and
+// x - x0 - x1 at most 8, so both differences are exact in FP32).
+__device__ __forceinline__ void bf16_split3_pair(float a, float b, unsigned &p0, unsigned &p1, unsigned &p2)
+{
+    float a0, b0, a1, b1, a2, b2;
+    p0 = bf16_pair(a, b, a0, b0);
+    const float da = a - a0, db = b - b0;
+    p1 = bf16_pair(da, db, a1, b1);
+    p2 = bf16_pair(da - a1, db - b1, a2, b2);
+}
+
+// Two FP32 values (already scaled into the FP16 range) as FP16 hi + lo
+// pieces, each rounded to nearest (v_cvt_pk_f16_f32): x = hi + lo + O(2^-22 x)
+__device__ __forceinline__ void f16_split2_pair(float a, float b, unsigned &hi, unsigned &lo)
+{
+    const f16x2 h = __builtin_convertvector(f32x2{a, b}, f16x2);
+    const f32x2 hf = __builtin_convertvector(h, f32x2);
+    const f16x2 l = __builtin_convertvector(f32x2{a - hf.x, b - hf.y}, f16x2);
+    hi = __builtin_bit_cast(unsigned, h);
+    lo = __builtin_bit_cast(unsigned, l);
+}
 
 template <int P, int F, typename C>
 __device__ __forceinline__ XOp<P, F> make_op(const TArgs &a)
@@ -107,13 +143,11 @@ __device__ __forceinline__ XOp<P, F> make_op(const TArgs &a)
             o.hi[e] = h;
             o.lo[e] = (_Float16)(r - (double)h);
         } else {
-            const float rf = (float)r;
-            const float r0 = bf16_trunc(rf);
-            const float r1 = bf16_trunc(rf - r0);
-            const float r2 = rf - r0 - r1;
-            o.b0[e] = bf16_bits(r0);
-            o.b1[e] = bf16_bits(r1);
-            o.b2[e] = bf16_bits(r2);
+            unsigned p0, p1, p2;
+            bf16_split3_pair((float)r, 0.f, p0, p1, p2);
+            o.b0[e] = (short)(p0 & 0xffffu);
+            o.b1[e] = (short)(p1 & 0xffffu);
+            o.b2[e] = (short)(p2 & 0xffffu);
         }
     }
     return o;
@@ -155,22 +189,23 @@ __device__ __forceinline__ void products(const float2 *x, const XOp<P, F> &op, f
         mx = fmaxf(mx, __shfl_xor(mx, 32));
         const int ex = mx > 0.f ? max(-100, min(100, ilogbf(mx))) : 0;
         const float sc = ldexpf(1.f, 14 - ex), inv = ldexpf(1.f, ex - 14);
-        f16x4 rh, rl, ih, il;
+        // pieces of elements (0, 1) and (2, 3), real and imaginary parts
+        unsigned rh[2], rl[2], ih[2], il[2];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float xr = x[e].x * sc, xi = x[e].y * sc;  // exact (powers of two)
-            const _Float16 hr = (_Float16)xr, hi_ = (_Float16)xi;
-            rh[e] = hr;
-            ih[e] = hi_;
-            rl[e] = (_Float16)(xr - (float)hr);
-            il[e] = (_Float16)(xi - (float)hi_);
+        for (int e = 0; e < 2; ++e) {  // scaling by powers of two is exact
+            f16_split2_pair(x[2 * e].x * sc, x[2 * e + 1].x * sc, rh[e], rl[e]);
+            f16_split2_pair(x[2 * e].y * sc, x[2 * e + 1].y * sc, ih[e], il[e]);
         }
-        re = __builtin_amdgcn_mfma_f32_16x16x16f16(rh, op.hi, re, 0, 0, 0);
-        re = __builtin_amdgcn_mfma_f32_16x16x16f16(rh, op.lo, re, 0, 0, 0);
-        re = __builtin_amdgcn_mfma_f32_16x16x16f16(rl, op.hi, re, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x16f16(ih, op.hi, im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x16f16(ih, op.lo, im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x16f16(il, op.hi, im, 0, 0, 0);
+        const f16x4 rhv = __builtin_bit_cast(f16x4, make_uint2(rh[0], rh[1]));
+        const f16x4 rlv = __builtin_bit_cast(f16x4, make_uint2(rl[0], rl[1]));
+        const f16x4 ihv = __builtin_bit_cast(f16x4, make_uint2(ih[0], ih[1]));
+        const f16x4 ilv = __builtin_bit_cast(f16x4, make_uint2(il[0], il[1]));
+        re = __builtin_amdgcn_mfma_f32_16x16x16f16(rlv, op.hi, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f32_16x16x16f16(rhv, op.lo, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f32_16x16x16f16(rhv, op.hi, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x16f16(ilv, op.hi, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x16f16(ihv, op.lo, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x16f16(ihv, op.hi, im, 0, 0, 0);
         // result rows 4 g + r belong to lines 4 g + r, whose scale lane 4 g + r holds
         const int g = (threadIdx.x & 63) >> 4;
         scale_back.x = __shfl(inv, 4 * g + 0);
@@ -178,19 +213,19 @@ __device__ __forceinline__ void products(const float2 *x, const XOp<P, F> &op, f
         scale_back.z = __shfl(inv, 4 * g + 2);
         scale_back.w = __shfl(inv, 4 * g + 3);
     } else {
-        bf16x4 r0, r1, r2, i0, i1, i2;
+        // pieces of elements (0, 1) and (2, 3), real and imaginary parts
+        unsigned q0[2], q1[2], q2[2], j0[2], j1[2], j2[2];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float xr = x[e].x, xi = x[e].y;
-            const float a0 = bf16_trunc(xr), a1 = bf16_trunc(xr - a0);
-            const float c0 = bf16_trunc(xi), c1 = bf16_trunc(xi - c0);
-            r0[e] = bf16_bits(a0);
-            r1[e] = bf16_bits(a1);
-            r2[e] = bf16_bits(xr - a0 - a1);  // exact: the last 8 significant bits
-            i0[e] = bf16_bits(c0);
-            i1[e] = bf16_bits(c1);
-            i2[e] = bf16_bits(xi - c0 - c1);
+        for (int e = 0; e < 2; ++e) {
+            bf16_split3_pair(x[2 * e].x, x[2 * e + 1].x, q0[e], q1[e], q2[e]);
+            bf16_split3_pair(x[2 * e].y, x[2 * e + 1].y, j0[e], j1[e], j2[e]);
         }
+        const bf16x4 r0 = __builtin_bit_cast(bf16x4, make_uint2(q0[0], q0[1]));
+        const bf16x4 r1 = __builtin_bit_cast(bf16x4, make_uint2(q1[0], q1[1]));
+        const bf16x4 r2 = __builtin_bit_cast(bf16x4, make_uint2(q2[0], q2[1]));
+        const bf16x4 i0 = __builtin_bit_cast(bf16x4, make_uint2(j0[0], j0[1]));
+        const bf16x4 i1 = __builtin_bit_cast(bf16x4, make_uint2(j1[0], j1[1]));
+        const bf16x4 i2 = __builtin_bit_cast(bf16x4, make_uint2(j2[0], j2[1]));
         // x_a R_b with a + b <= 2, smallest terms first
         re = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r2, op.b0, re, 0, 0, 0);
         re = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r1, op.b1, re, 0, 0, 0);
@@ -207,14 +242,29 @@ __device__ __forceinline__ void products(const float2 *x, const XOp<P, F> &op, f
     }
 }
 
-// Stage 1 on the matrix cores: each wave takes groups of 16 consecutive
-// input lines of the item (lines past the end are loaded clamped and not
-// stored); every lane of the wave takes part in every product.  xn holds
-// the lane's elements of the wave's first group on entry; each next group
-// is loaded while the current one is computed.
+// Groups of 16 lines a wave loads at once in stage 1: a work item's lines
+// (about 225 at the tuned tiles of p = 9) usually fit one batch, so stage 1
+// waits for memory once, as the VALU kernel's one-line-per-thread pass does.
+constexpr int kBatch = 4;
+
+// The lane's elements of the wave's batch of groups starting at line `base`
 template <int P, int F>
-__device__ __forceinline__ void stage1_xdl(const TArgs &a, const Item2D &it, float2 *xn, float2 *Y,
-                                           const int *s_bits, const XOp<P, F> &op)
+__device__ __forceinline__ void load_batch(const TArgs &a, const Item2D &it, int base, int nlines,
+                                           float2 (&x)[kBatch][XLane<P, F>::NE])
+{
+    const int i = threadIdx.x & 15;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) load_elems<P, F>(a, it, min(base + 16 * kWaves * b + i, nlines - 1), x[b]);
+}
+
+// Stage 1 on the matrix cores: wave w takes the groups of 16 consecutive
+// input lines starting at 16 w, 16 (w + kWaves), ... (lines past the end
+// are loaded clamped and not stored); every lane of the wave takes part in
+// every product.  x holds the lane's elements of the wave's first batch on
+// entry.
+template <int P, int F>
+__device__ __forceinline__ void stage1_xdl(const TArgs &a, const Item2D &it, float2 (&x)[kBatch][XLane<P, F>::NE],
+                                           float2 *Y, const XOp<P, F> &op)
 {
     constexpr int NE = XLane<P, F>::NE, Q = P - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -222,40 +272,42 @@ __device__ __forceinline__ void stage1_xdl(const TArgs &a, const Item2D &it, flo
     const int rowlen = it.nin * P;
     const int nlines = it.R * rowlen;
     const int ysz = it.R * it.nin * P * P;  // one t2 half of Y
-    const float inv_rowlen = 1.0f / (float)rowlen;
     const bool jv = XCols<P>::valid(i);
     const int jt = XCols<P>::t2(i), jm = XCols<P>::m(i);
-    for (int g0 = 16 * wave; g0 < nlines; g0 += 16 * kWaves) {  // uniform in the wave
-        float2 x[NE];
+    for (int base = 16 * wave; base < nlines; base += 16 * kWaves * kBatch) {  // uniform in the wave
+        if (base != 16 * wave) load_batch<P, F>(a, it, base, nlines, x);
 #pragma unroll
-        for (int e = 0; e < NE; ++e) x[e] = xn[e];
-        load_elems<P, F>(a, it, min(g0 + 16 * kWaves + i, nlines - 1), xn);
-        f32x4 re, im;
-        float4 sb;
-        products<P, F>(x, op, re, im, sb);
-        // dot rows: lines g0 + 4 g + r, column i
-        if (jv) {
-            const float s4[4] = {sb.x, sb.y, sb.z, sb.w};
+        for (int b = 0; b < kBatch; ++b) {
+            const int g0 = base + 16 * kWaves * b;
+            if (g0 >= nlines) break;  // uniform in the wave
+            f32x4 re, im;
+            float4 sb;
+            products<P, F>(x[b], op, re, im, sb);
+            // dot rows: lines g0 + 4 g + r, column i.  Both positions t2 are
+            // stored whether or not the line's row a' needs them (stage 2
+            // reads only the needed ones; Y holds both).
+            if (jv) {
+                const float s4[4] = {sb.x, sb.y, sb.z, sb.w};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int w = g0 + 4 * g + r;
-                if (w >= nlines) continue;
-                const int row = (int)(((float)w + 0.5f) * inv_rowlen);
-                if (!((s_bits[row] >> (4 + jt)) & 1)) continue;
-                Y[jt * ysz + w * P + jm] = make_float2(re[r] * s4[r], im[r] * s4[r]);
+                for (int r = 0; r < 4; ++r) {
+                    const int w = g0 + 4 * g + r;
+                    if (w >= nlines) continue;
+                    // only the FP16 format scales its lines
+                    Y[jt * ysz + w * P + jm] = F == kF16X2 ? make_float2(re[r] * s4[r], im[r] * s4[r])
+                                                           : make_float2(re[r], im[r]);
+                }
             }
-        }
-        // copy rows: the lane's own elements n of line g0 + i go to row 2n
-        // (t2 = 0) and 2n - q (t2 = 1)
-        const int v = g0 + i;
-        if (v < nlines) {
-            const int bits = s_bits[(int)(((float)v + 0.5f) * inv_rowlen)];
+            // copy rows: the lane's own elements n of line g0 + i go to row 2n
+            // (t2 = 0) and 2n - q (t2 = 1)
+            const int v = g0 + i;
+            if (v < nlines) {
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const int n = XLane<P, F>::elem(e, g);
-                if (n >= P) continue;
-                if ((bits & 16) && 2 * n <= Q) Y[v * P + 2 * n] = x[e];
-                if ((bits & 32) && 2 * n >= Q) Y[ysz + v * P + 2 * n - Q] = x[e];
+                for (int e = 0; e < NE; ++e) {
+                    const int n = XLane<P, F>::elem(e, g);
+                    if (n >= P) continue;
+                    if (2 * n <= Q) Y[v * P + 2 * n] = x[b][e];
+                    if (2 * n >= Q) Y[ysz + v * P + 2 * n - Q] = x[b][e];
+                }
             }
         }
     }
@@ -272,11 +324,12 @@ __device__ __forceinline__ void translate2d_xdl_item(const TArgs &a, int64_t gid
     Item2D it = item2d(a, gid);
     const Slots2D h = load_slots(a, it);
     __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the lines'
-    float2 xn[XLane<P, F>::NE];
-    load_elems<P, F>(a, it, min(16 * (int)(threadIdx.x >> 6) + (int)(threadIdx.x & 15), it.R * it.nin * P - 1), xn);
+    // the wave's first batch of lines, in flight through the table fill
+    float2 x[kBatch][XLane<P, F>::NE];
+    load_batch<P, F>(a, it, 16 * (int)(threadIdx.x >> 6), it.R * it.nin * P, x);
     const XOp<P, F> op = make_op<P, F, C>(a);
     fill_tables<RHO1>(a, it, h, tb);
-    stage1_xdl<P, F>(a, it, xn, Y, tb.bits, op);
+    stage1_xdl<P, F>(a, it, x, Y, op);
     __syncthreads();
     stage2_2d<P, RHO1, float, C>(a, it, Y, tb);
 }
