@@ -4,13 +4,14 @@ exchanged (the kernel of eq. (1) is symmetric in x and k) and the sign
 reversed by conjugation, and against the forward transform through the dot
 product <B f, g> = <f, B^H g>.
 
-Bars: FP64 vs the oracle butterfly O2 rel-l2 <= 1e-10; "mixed" <= 2e-6;
+Bars: FP64 vs the oracle butterfly O2 rel-l2 <= 1e-10; the reduced
+precisions within 3x the deviation measured on an MI355X for the same case;
 every precision vs the direct sum at the method's accuracy for p.
 """
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import rel_l2, within_measured
 from paper_0801_1524_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -32,13 +33,21 @@ def oracle_adjoint(oracle_mod, P, g):
     return np.conj(oracle_mod.Butterfly(P.d, P.N, P.p, P.k, P.x).run(np.conj(g)))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+# rel-l2 vs the exchanged O2 at c1 (p = 7, leaf start), measured on an MI355X
+MEASURED_ADJ = {"mixed": 1.66e-7, "fp32": 4.32e-7, "fp16x2": 4.86e-7, "bf16x3": 2.25e-7}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32", "fp16x2", "bf16x3"])
 def test_adjoint_vs_oracle_and_direct(bf, oracle_mod, precision):
     P = synth.config("c1")
     g = synth.gaussian_sources(P.nx, 77)
     with bf.Plan(P.d, P.N, P.p, P.x, P.k, precision) as plan:
         v = plan.execute_adjoint(g).cpu().numpy()
-    assert rel_l2(v, oracle_adjoint(oracle_mod, P, g)) <= {"fp64": 1e-10, "mixed": 2e-6}[precision]
+    err = rel_l2(v, oracle_adjoint(oracle_mod, P, g))
+    if precision == "fp64":
+        assert err <= 1e-10
+    else:
+        within_measured(err, MEASURED_ADJ[precision], f"adjoint c1 {precision}")
     S = np.arange(0, P.nk, 7)
     vd = np.conj(oracle_mod.direct(P.k, P.x, np.conj(g), P.N, S))
     assert rel_l2(v[S], vd) <= EPS[P.p]

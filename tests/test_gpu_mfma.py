@@ -3,18 +3,20 @@ BFSFT_TRANSLATE=mfma, against the CPU oracle and against the VALU kernel.
 
 Bars: FP64 vs the oracle butterfly O2 rel-l2 <= 1e-10 (the two kernels
 compute the same operations in a different order, so only rounding
-differs); "mixed" vs O2 <= 2e-6 as for the VALU kernel; MFMA vs VALU at
-FP64 <= 1e-13.
+differs); "mixed" vs O2 within 3x the deviation measured on an MI355X for
+the same case; MFMA vs VALU at FP64 <= 1e-13.
 """
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import rel_l2, within_measured
 from paper_0801_1524_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 EPS = {5: 6e-3, 6: 1e-3, 7: 3e-4, 8: 2e-5, 9: 1.5e-6}
+# rel-l2 of the mixed path vs O2, measured on an MI355X (the bar is 3x)
+MEASURED_MIXED = {"c1": 1.85e-7, "one": 4.22e-8}
 
 
 @pytest.fixture(scope="module")
@@ -50,7 +52,11 @@ def test_mfma_every_p_fp64_vs_oracle(bf, oracle_mod, monkeypatch, p):
 def test_mfma_c1_vs_oracle_and_direct(bf, oracle_mod, monkeypatch, precision):
     P = synth.config("c1")
     u = run(bf, P, precision, "mfma", monkeypatch)
-    assert rel_l2(u, oracle_u(oracle_mod, P)) <= {"fp64": 1e-10, "mixed": 2e-6}[precision]
+    err = rel_l2(u, oracle_u(oracle_mod, P))
+    if precision == "fp64":
+        assert err <= 1e-10
+    else:
+        within_measured(err, MEASURED_MIXED["c1"], "mfma c1 mixed")
     S = synth.error_subset(P.nx, 1)
     assert rel_l2(u[S], oracle_mod.direct(P.x, P.k, P.f, P.N, S)) <= EPS[P.p]
 
@@ -104,7 +110,8 @@ def test_mfma_faces_clusters_single(bf, oracle_mod, monkeypatch):
     assert rel_l2(run(bf, P, "fp64", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 1e-10
     P = synth.Problem("one", 2, 64, 5, np.array([[3.25, 60.5]]), np.array([[17.0, 0.0]]),
                       np.array([1.0 - 2.0j]))
-    assert rel_l2(run(bf, P, "mixed", "mfma", monkeypatch), oracle_u(oracle_mod, P)) <= 2e-6
+    within_measured(rel_l2(run(bf, P, "mixed", "mfma", monkeypatch), oracle_u(oracle_mod, P)),
+                    MEASURED_MIXED["one"], "mfma single point mixed")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -4,13 +4,14 @@ procedure of Section 2.1), then the butterfly from there.  The start level
 is chosen by the plan (BFSFT_START_LEVEL unset) or forced; the oracle runs
 the same sweep with the same start level.
 
-Bars: FP64 vs the oracle O2 rel-l2 <= 1e-10; "mixed" <= 2e-6; the 1e-6 gate
+Bars: FP64 vs the oracle O2 rel-l2 <= 1e-10; the reduced precisions within 3x
+the deviation measured on an MI355X for the same case; the 1e-6 gate
 on the c2 error subset against the direct sum.
 """
 import numpy as np
 import pytest
 
-from conftest import rel_l2
+from conftest import rel_l2, within_measured
 from paper_0801_1524_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -64,11 +65,17 @@ def test_auto_start_is_above_the_leaves_at_one_sample_per_unit(bf, monkeypatch):
     assert s0 >= 1
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+# rel-l2 vs O2 at the same start level, measured on an MI355X (the bar is 3x)
+MEASURED_C1_S3 = {"mixed": 1.5e-7, "fp32": 3.78e-7, "fp16x2": 4.38e-7, "bf16x3": 2.01e-7}
+# (the largest over the seven transforms)
+MEASURED_BATCH_S2 = {"mixed": 1.53e-7, "bf16x3": 2.89e-7}
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32", "fp16x2", "bf16x3"])
 def test_c1_lower_precisions(bf, oracle_mod, monkeypatch, precision):
     P = synth.config("c1")
     u, s0 = run(bf, P, precision, 3, monkeypatch)
-    assert rel_l2(u, oracle_u(oracle_mod, P, s0)) <= {"mixed": 2e-6, "fp32": 3e-5}[precision]
+    within_measured(rel_l2(u, oracle_u(oracle_mod, P, s0)), MEASURED_C1_S3[precision], f"c1 start 3 {precision}")
 
 
 @pytest.mark.parametrize("N,p,start", [(1000, 7, 2), (3001, 9, 3), (512, 5, 9)])
@@ -148,7 +155,7 @@ def _split(u, probs):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "bf16x3"])
 def test_batched_forced_start_vs_serial_and_oracle(bf, oracle_mod, monkeypatch, precision):
     """Every transform starts 2 levels above its leaves: the batched graph
     (a direct-sum launch for all transforms, then the steps) equals the same
@@ -161,10 +168,12 @@ def test_batched_forced_start_vs_serial_and_oracle(bf, oracle_mod, monkeypatch, 
     us = B.execute(f, serial=True).cpu().numpy()
     B.close()
     assert rel_l2(ug, us) <= 1e-14
-    tol = {"fp64": 1e-10, "mixed": 2e-6}[precision]
     for q, u in zip(probs, _split(ug, probs)):
         ub = oracle_mod.Butterfly(2, q.N, q.p, q.x, q.k).run(q.f, start_level=2)
-        assert rel_l2(u, ub) <= tol, (q.name, q.N)
+        if precision == "fp64":
+            assert rel_l2(u, ub) <= 1e-10, (q.name, q.N)
+        else:
+            within_measured(rel_l2(u, ub), MEASURED_BATCH_S2[precision], f"batched start 2 {precision} {q.name}")
 
 
 def test_batched_auto_start_vs_serial_and_direct(bf, oracle_mod, monkeypatch):

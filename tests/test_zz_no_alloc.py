@@ -33,9 +33,9 @@ def run_both(bf, P, precision):
         return ref.cpu().numpy(), out.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("precision", ["mixed", "fp64", "bf16x3"])
 def test_noalloc_matches_execute_two_calls(bf, precision):
-    big = synth.config("c1") if precision == "mixed" else synth.curve_problem(1024, 7, seed=3)
+    big = synth.config("c1") if precision != "fp64" else synth.curve_problem(1024, 7, seed=3)
     small = synth.config("c0")
     for P in (big, small):  # the second call is the smaller input
         ref, got = run_both(bf, P, precision)
