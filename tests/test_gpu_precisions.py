@@ -207,3 +207,21 @@ def test_split_formats_level_potentials_and_edges(bf, oracle_mod, precision):
     P0 = synth.Problem("none", 2, N, 6, x, k[:0], f[:0])
     u, _ = gpu_u(bf, P0, precision)
     assert not np.any(u)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32", "fp16x2", "bf16x3"])
+def test_power_of_two_scaling_is_exact(bf, precision):
+    """The transform is linear and every rounding is scale-free for powers of
+    two: sources scaled by 2^k give outputs scaled by exactly 2^k, bit for
+    bit, in every precision (k = +-40 keeps the FP32 state far from overflow
+    and underflow).  In FP16X2 this pins the per-line power-of-two scaling of
+    the matrix-core operands: a line scaled by 2^k must split into the same
+    FP16 pieces."""
+    import torch
+    P = synth.config("c1")
+    with bf.Plan(P.d, P.N, P.p, P.x, P.k, precision) as plan:
+        f = torch.from_numpy(P.f).to("cuda")
+        u = plan.execute(f).cpu().numpy()
+        for k in (40, -40):
+            uk = plan.execute(f * 2.0 ** k).cpu().numpy()
+            assert np.array_equal(uk, u * 2.0 ** k), (precision, k)
