@@ -454,7 +454,9 @@ def main():
         "config": {"workload": wl_text,
                    "nx": P.nx, "nk": P.nk, "levels": r["info"]["levels"], "precision": head,
                    "state_dtype": "f64" if head == "fp64" else "f32",
-                   "start_level": r["info"]["start_level"]},
+                   "start_level": r["info"]["start_level"],
+                   # direct sums of the start level: 0 VALU, 1 FP64 matrix cores
+                   "start_kernel": r["info"]["start_kernel"]},
         "err_rel_l2": errs[head],
         "gate_passed": errs[head] is not None and errs[head] <= GATE,
         "roofline": dict(roofline(r, head, wl), copy_GBps=copy_gbs, copy_elem_bytes=elem,

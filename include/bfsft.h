@@ -89,6 +89,8 @@ typedef struct {
     int level_lds_kb[BFSFT_MAX_LEVELS];   /* single plan: tile LDS budget of level l (tuned) */
     int start_level;                      /* single plan: the sweep starts at T_K level
                                              levels - start_level (0: at the leaves) */
+    int start_kernel;                     /* single plan with start_level > 0: direct sums on
+                                             0 the VALU, 1 the FP64 matrix cores */
 } bfsft_info;
 
 /*
@@ -124,7 +126,9 @@ typedef struct {
  * plain procedure of Section 2.1), with start_level chosen from the tree
  * sizes by a fixed cost model (0 = the leaf start of Section 2.2) or forced
  * by BFSFT_START_LEVEL=n (at most 18); results differ between start levels
- * at the level of the method's error, not by rounding;
+ * at the level of the method's error, not by rounding; the direct sums run
+ * on the FP64 matrix cores (2D p <= 12, 3D p <= 5) or on the VALU
+ * (BFSFT_DIRECT=valu forces the VALU kernel; the two differ by rounding);
  * BFSFT_TUNE_CACHE names the text file caching tuned choices (default
  * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget.
  */

@@ -55,6 +55,7 @@ class Info(ctypes.Structure):
         ("lds_kb", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
         ("level_kernel", ctypes.c_int * MAX_LEVELS), ("level_lds_kb", ctypes.c_int * MAX_LEVELS),
         ("start_level", ctypes.c_int),
+        ("start_kernel", ctypes.c_int),
     ]
 
 
@@ -198,6 +199,7 @@ def _info_dict(info: Info) -> dict:
         "lds_kb": info.lds_kb, "wg_per_cu": info.wg_per_cu,
         "level_kernel": list(info.level_kernel[:L]), "level_lds_kb": list(info.level_lds_kb[:L]),
         "start_level": info.start_level,
+        "start_kernel": info.start_kernel,
     }
 
 

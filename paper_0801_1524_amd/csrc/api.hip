@@ -473,37 +473,82 @@ void build_tiles(bfsft_plan *P, int lds_bytes)
 //   leaf initialisation (s0 = 0): 5.7e-3 per source and grid point.
 // A start above the leaves is taken only if it saves at least 3 % of the
 // modelled time.  BFSFT_START_LEVEL=n forces n (clamped to [0, min(L, kStartMax)]).
-int choose_start(const bfsft_plan *P)
+// Start level and direct-sum kernel from a cost model of the measured
+// kernel times (ns): translations per output pair, VALU direct sums per
+// (pair, source, grid line), matrix-core direct sums per padded complex
+// multiply-add on the busiest SIMD (about 45 ns per FP64 MFMA with two
+// consumer waves per SIMD, a third more with one) plus the producers' work
+// per step (which the SIMD does not overlap with the products).  The
+// matrix-core kernel is taken in 3D and where at least 5 row tiles give two
+// consumer waves per SIMD; BFSFT_DIRECT restricts the choice.
+StartChoice choose_start(const bfsft_plan *P)
 {
-    if (P->nx == 0 || P->nk == 0) return 0;
+    StartChoice c;
+    if (P->nx == 0 || P->nk == 0) return c;
     const int L = P->L, d = P->d;
-    if (const char *e = std::getenv("BFSFT_START_LEVEL")) {
-        char *end = nullptr;
-        const long v = std::strtol(e, &end, 10);
-        if (end != e) return (int)std::max(0L, std::min((long)std::min(L, kStartMax), v));
-    }
+    // a transform of a batched plan: its direct sums run in the batched
+    // graph's VALU launch
+    const int kinds = P->valu_only ? 1 : direct_kinds(d, P->p);
+    int dev = 0, ncu = 0;
+    BF_HIP(hipGetDevice(&dev));
+    BF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    ncu = std::max(1, ncu);
     const double p = P->p;
     const double lines = d == 2 ? p : p * p;
     auto pairs = [&](int l) { return (double)P->tx.count[L - l] * (double)P->tk.count[l]; };
     const double tr = (d == 2 ? 6.4e-4 : 1.54e-3) * std::pow(p, d + 1);
     const double dr = 0.0066 * (1.0 + 0.15 * (d - 2));
+    const int pd = d == 2 ? P->p * P->p : P->p * P->p * P->p;
+    const int nt = (pd + 15) / 16;
+    const int maxc = nt <= 6 ? 8 : 4;
+    auto direct_cost = [&](int l0, int s, int kind) {
+        const double nk = (double)P->nk, nB = (double)P->tk.count[l0], nA = (double)P->tx.count[s];
+        if (kind == 0) return dr * pairs(l0) * (nk / nB) * lines;
+        const double tiles = std::ceil(nA / 16.0);
+        const double w = std::min<double>(maxc, tiles);
+        const double full = std::floor(tiles / w), rem = tiles - full * w;
+        const double simd_rows = 16.0 * (full * std::ceil(w / 4.0) + std::ceil(rem / 4.0));
+        const double blocks = std::ceil(tiles / w);
+        const double load = simd_rows * (nk + 1.5 * nB) * 16.0 * nt;  // complex multiply-adds
+        const double steps = blocks * (nk / 16.0 + 0.5 * nB);
+        const double t_mfma = 45.0 * (d == 2 && w <= 4 ? 1.33 : 1.0);
+        return t_mfma * load / (256.0 * ncu) + steps / ncu * (350.0 * w + 300.0);
+    };
+    // the kernel at start level s: in 2D the matrix cores from 5 row tiles
+    // on (with fewer, one consumer wave per SIMD, the VALU kernel measures
+    // faster); in 3D the cheaper of the two in the model
+    auto kind_at = [&](int s) {
+        if (!(kinds & 2)) return 0;
+        if (!(kinds & 1)) return 1;
+        if (d == 2) return P->tx.count[s] > 64 ? 1 : 0;
+        return direct_cost(L - s, s, 1) < direct_cost(L - s, s, 0) ? 1 : 0;
+    };
+    if (const char *e = std::getenv("BFSFT_START_LEVEL")) {
+        char *end = nullptr;
+        const long v = std::strtol(e, &end, 10);
+        if (end != e) {
+            c.s0 = (int)std::max(0L, std::min((long)std::min(L, kStartMax), v));
+            c.kind = c.s0 > 0 ? kind_at(c.s0) : 0;
+            return c;
+        }
+    }
     std::vector<double> below(L + 1, 0.0);  // below[l0]: translations producing levels < l0
     for (int l = 1; l <= L; ++l) below[l] = below[l - 1] + tr * pairs(l - 1);
     const double leaf_cost = 5.7e-3 * (double)P->nk * std::pow(p, d) + below[L];
-    int best = 0;
     double best_cost = leaf_cost;
     for (int s = 1; s <= std::min(L, kStartMax); ++s) {
-        const int l0 = L - s;
-        const double per_box = (double)P->nk / (double)P->tk.count[l0];
-        const double cost = dr * pairs(l0) * per_box * lines + below[l0];
+        const int l0 = L - s, kind = kind_at(s);
+        const double cost = direct_cost(l0, s, kind) + below[l0];
         if (cost < best_cost) {
             best_cost = cost;
-            best = s;
+            c.s0 = s;
+            c.kind = kind;
         }
     }
     // the leaf start of the paper unless the model predicts a clear gain
     // (it is within a few per cent of the measured times)
-    return best_cost < 0.97 * leaf_cost ? best : 0;
+    if (!(best_cost < 0.97 * leaf_cost)) c = StartChoice{};
+    return c;
 }
 
 void build_plan(bfsft_plan *P, const double *x, const double *k)
@@ -529,7 +574,11 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     const size_t bytes = state_bytes(P);
     P->buf[0] = P->arena.alloc(bytes);
     P->buf[1] = P->arena.alloc(bytes);
-    build_start(P->start, P->tk, choose_start(P), P->d, P->p - 1, P->rho, P->arena, s);
+    const StartChoice sc = choose_start(P);
+    P->start.kind = sc.kind;
+    build_start(P->start, P->tk, sc.s0, P->d, P->p - 1, P->rho, P->arena, s);
+    if (P->start.kind == 1 && P->start.s0 > 0)
+        build_direct_steps(P->start, P->tx, P->tk, P->d, P->p, P->arena, s);
     build_tiles(P, translate_default_lds());
     BF_HIP(hipStreamSynchronize(s));
 }
@@ -573,7 +622,11 @@ bfsft_plan *make_adjoint(bfsft_plan *P)
             if (state_bytes(A) > state_bytes(P)) throw Error{BFSFT_EDEVICE, "adjoint state larger than the plan's"};
             A->buf[0] = P->buf[0];
             A->buf[1] = P->buf[1];
-            build_start(A->start, A->tk, choose_start(A), A->d, A->p - 1, A->rho, A->arena, A->stream);
+            const StartChoice sc = choose_start(A);
+            A->start.kind = sc.kind;
+            build_start(A->start, A->tk, sc.s0, A->d, A->p - 1, A->rho, A->arena, A->stream);
+            if (A->start.kind == 1 && A->start.s0 > 0)
+                build_direct_steps(A->start, A->tx, A->tk, A->d, A->p, A->arena, A->stream);
         }
         build_tiles(A, translate_default_lds());
         if (A->nx > 0 && A->nk > 0 && autotune_enabled()) autotune_single(A);
@@ -829,6 +882,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         o->device_bytes = P->arena.bytes + (P->adj ? P->adj->arena.bytes : 0);
         o->lds_kb = P->lds / 1024;
         o->start_level = P->start.s0;
+        o->start_kernel = P->start.s0 > 0 ? P->start.kind : 0;
         for (int l = 0; l < P->L && l < (int)P->kind.size(); ++l) {
             o->level_kernel[l] = P->kind[l];
             o->level_lds_kb[l] = P->lds_level[l] / 1024;

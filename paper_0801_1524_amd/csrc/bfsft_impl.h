@@ -176,6 +176,13 @@ void launch_translate(const Launch &c, const LevelArgs &a);
 // Start of the sweep s0 levels above the leaves (s0 = 0: the leaves).
 struct StartLevel {
     int s0 = 0;
+    int kind = 0;               // direct-sum kernel: 0 VALU, 1 FP64 matrix cores
+    // matrix-core kernel: its steps (one chunk of at most 16 sources of a box
+    // B for one block of A rows), in order, and each work-group's range of them
+    int4 *steps = nullptr;      // [nsteps] x first source, y count | first << 8 | last << 9,
+                                //   z box b, w row block
+    int32_t *wg_first = nullptr;// [nwg + 1] first step of every work-group
+    int nwg = 0, nwaves = 0;
     int2 *box_leaf = nullptr;   // [count_K[L - s0]] leaf range of every box of T_K level L - s0
     int32_t *sm = nullptr;      // [npts][d] leaf index mod 2^s0 of every source (sorted order)
     double *sloc = nullptr;     // [npts][d] offset inside its leaf (sorted order)
@@ -187,12 +194,22 @@ void build_start(StartLevel &st, const Tree &tk, int s0, int d, int q, double rh
 void launch_direct(const Launch &c, const StartLevel &st, const double *f, const Tree &tx, const Tree &tk,
                    int64_t N, void *state);
 
+// direct-sum kernels: the VALU one takes every (d, p); the matrix-core one
+// 2D p <= 12 and 3D p <= 5.  Bit 0: VALU allowed, bit 1: matrix cores;
+// BFSFT_DIRECT=valu or =mfma allows one only (mfma falls back to valu where
+// unsupported).
+bool direct_mfma_supported(int d, int p);
+int direct_kinds(int d, int p);
+
 // one transform of a (batched) direct start-level launch
 struct DirectDesc {
     int s0, L;
     int64_t N, nA, nB;          // pairs: T_X boxes of level s0 x T_K boxes of level L - s0
     const uint64_t *xkeys;      // T_X keys of level s0
     const int2 *box_leaf;
+    const int4 *steps;          // matrix-core kernel only (single plans)
+    const int32_t *wg_first;
+    int nwg, nwaves;
     const int32_t *leaf_beg;
     const int32_t *perm;
     const int32_t *sm;
@@ -206,6 +223,10 @@ struct DirectDesc {
 DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, const Tree &tk, int64_t N,
                        const Tables &tb, void *state);
 int64_t direct_items(int d, int p, const DirectDesc &dd);
+void launch_direct_mfma(const Launch &c, const DirectDesc &dd);
+// the matrix-core kernel's step list for start level st.s0 (st.kind == 1)
+void build_direct_steps(StartLevel &st, const Tree &tx, const Tree &tk, int d, int p, Arena &arena,
+                        hipStream_t s);
 void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t *prefix, int n, int64_t total);
 
 // 2D translation with stage 1 on the matrix cores in the FP32, FP16X2 or

@@ -428,6 +428,9 @@ __device__ __forceinline__ DirectDesc load_direct_desc(const DirectDesc *descs, 
     d.nB = p->nB;
     d.xkeys = p->xkeys;
     d.box_leaf = p->box_leaf;
+    d.steps = nullptr;
+    d.wg_first = nullptr;
+    d.nwg = d.nwaves = 0;
     d.leaf_beg = p->leaf_beg;
     d.perm = p->perm;
     d.sm = p->sm;
@@ -686,6 +689,10 @@ DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, co
     d.nB = tk.count[tk.L - st.s0];
     d.xkeys = tx.keys[st.s0];
     d.box_leaf = st.box_leaf;
+    d.steps = st.steps;
+    d.wg_first = st.wg_first;
+    d.nwg = st.nwg;
+    d.nwaves = st.nwaves;
     d.leaf_beg = tk.leaf_beg;
     d.perm = tk.perm;
     d.sm = st.sm;
@@ -710,6 +717,10 @@ void launch_direct(const Launch &c, const StartLevel &st, const double *f, const
                    int64_t N, void *state)
 {
     const DirectDesc dd = direct_desc(st, f, tx, tk, N, *c.tb, state);
+    if (st.kind == 1) {
+        launch_direct_mfma(c, dd);
+        return;
+    }
     const int64_t n = direct_items(c.d, c.p, dd);
     if (n == 0) return;
     const bool f32 = c.precision != BFSFT_FP64;

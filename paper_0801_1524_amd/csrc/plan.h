@@ -78,7 +78,11 @@ void build_plan(bfsft_plan *P, const double *x, const double *k);
 void release_plan(bfsft_plan *P);
 int ceil_log2(int64_t N);
 int64_t env_cap();
-int choose_start(const bfsft_plan *P);
+// start level of the sweep and its direct-sum kernel (0 VALU, 1 matrix cores)
+struct StartChoice {
+    int s0 = 0, kind = 0;
+};
+StartChoice choose_start(const bfsft_plan *P);
 
 // autotuning cache (text file, one "key value..." line per entry)
 bool tune_lookup(const std::string &key, std::vector<int> &vals);
