@@ -310,6 +310,26 @@ def roofline(res, precision, workload):
     return out
 
 
+def direct_roofline(res, mfma_tflops):
+    """The start level's direct sums against the FP64 matrix-core rate
+    measured by the library's rate kernel (two waves per SIMD, 12 chains)
+    and the published peak: useful complex multiply-adds (pairs x sources x
+    p^d) x 8 flops over the launch time.  Null for a leaf start."""
+    info, tm = res["info"], res["timing"]
+    s0 = info["start_level"]
+    if s0 == 0:
+        return None
+    L, d, p = info["levels"], info["d"], info["p"]
+    t = tm["leaf_ms"] / tm["executes"] / 1e3
+    flops = info["x_boxes"][s0] * info["nk"] * p ** d * 8.0
+    kernel = "k_direct_mfma" if info["start_kernel"] == 1 else "k_direct"
+    return {"kernel": kernel, "start_level": s0, "pairs": info["pairs"][L - s0],
+            "avg_launch_ms": round(t * 1e3, 4), "useful_flops_per_launch": flops,
+            "tflops": round(flops / t / 1e12, 2),
+            "measured_mfma_f64_tflops": mfma_tflops, "published_peak_tflops": 78.6,
+            "frac_of_measured": round(flops / t / 1e12 / mfma_tflops, 4) if mfma_tflops else None}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -438,6 +458,12 @@ def main():
     elem = 16 if head == "fp64" else 8
     copy_gbs = copy_rate(bf, elem)
     log(f"[bench] streaming copy kernel ({elem} B elements): {copy_gbs} GB/s (read + write)")
+    mfma_tf = round(bf.mfma_f64_rate(2, 20000), 2)
+    log(f"[bench] FP64 matrix-core rate (12 chains, 2 waves per SIMD): {mfma_tf} TFLOP/s")
+    direct = direct_roofline(r, mfma_tf)
+    if direct:
+        log(f"[bench] start-level direct sums ({direct['kernel']}): {direct['avg_launch_ms']} ms, "
+            f"{direct['tflops']} useful TFLOP/s ({direct['frac_of_measured']} of the measured rate)")
     line = {
         "metric": "outputs u_i/sec at rel-l2 err<=1e-6; mixed-precision vs FP64 GPU butterfly",
         "value": round(P.nx / (ms / 1e3), 1),
@@ -461,6 +487,7 @@ def main():
         "gate_passed": errs[head] is not None and errs[head] <= GATE,
         "roofline": dict(roofline(r, head, wl), copy_GBps=copy_gbs, copy_elem_bytes=elem,
                          frac_of_copy=round(roofline(r, head, wl)["achieved"] / copy_gbs, 4)),
+        "direct": direct,
         "cpu_baseline": base,
         "precisions": {k: {"outputs_per_s": round(P.nx / (v["ms_per_step"] / 1e3), 1),
                            "ms_per_step": round(v["ms_per_step"], 4),

@@ -283,6 +283,17 @@ int bfsft_timing_end(bfsft_plan *plan, double *out, int n);
  */
 int bfsft_copy_rate(int elem_bytes, int64_t bytes, int reps, void *stream, double *gbps);
 
+/*
+ * Measurement helper (not part of the method): the FP64 matrix-core rate
+ * that waves_per_simd (1..8) waves per SIMD reach with 12 independent
+ * chains of v_mfma_f64_16x16x4f64 each (the accumulator count of the
+ * matrix-core direct sums), the practical ceiling those sums are compared
+ * with.  Runs one short untimed and one timed launch of `iters` (1..2^20)
+ * rounds on `stream`, with a device buffer it allocates and frees; writes
+ * to *tflops (host) the FP64 TFLOP/s.  Synchronises the stream.
+ */
+int bfsft_mfma_f64_rate(int waves_per_simd, int iters, void *stream, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -108,6 +108,8 @@ def lib():
     L.bfsft_timing_end.restype = I
     L.bfsft_copy_rate.argtypes = [I, I64, I, P, ctypes.POINTER(ctypes.c_double)]
     L.bfsft_copy_rate.restype = I
+    L.bfsft_mfma_f64_rate.argtypes = [I, I, P, ctypes.POINTER(ctypes.c_double)]
+    L.bfsft_mfma_f64_rate.restype = I
     _lib = L
     return L
 
@@ -397,6 +399,17 @@ def copy_rate(elem_bytes: int = 8, nbytes: int = 1 << 30, reps: int = 5) -> floa
     out = ctypes.c_double()
     _check(lib().bfsft_copy_rate(int(elem_bytes), int(nbytes), int(reps),
                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(out)))
+    return out.value
+
+
+def mfma_f64_rate(waves_per_simd: int = 2, iters: int = 20000) -> float:
+    """FP64 TFLOP/s of 12 independent v_mfma_f64_16x16x4f64 chains per wave
+    at waves_per_simd waves per SIMD on the current GPU and stream: the
+    practical ceiling of the matrix-core direct sums."""
+    torch = _torch()
+    out = ctypes.c_double()
+    _check(lib().bfsft_mfma_f64_rate(int(waves_per_simd), int(iters),
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(out)))
     return out.value
 
 

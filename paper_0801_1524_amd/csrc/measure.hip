@@ -1,10 +1,14 @@
-// Measurement helper: the streaming bandwidth a plain read-and-write kernel
-// reaches on this GPU, at a given element size.  It is the practical memory
-// ceiling the translation kernels are compared with (they read each level's
-// state once and write the next level's once, with the same element sizes).
+// Measurement helpers: the streaming bandwidth a plain read-and-write kernel
+// reaches on this GPU, at a given element size, the practical memory ceiling
+// the translation kernels are compared with (they read each level's state
+// once and write the next level's once, with the same element sizes); and
+// the FP64 matrix-core rate sustained by independent 16 x 16 x 4 products,
+// the practical ceiling of the matrix-core direct sums.
 #include "bfsft_impl.h"
 
 #include <algorithm>
+#include <string>
+#include <vector>
 
 namespace bfsft {
 
@@ -30,6 +34,31 @@ __global__ __launch_bounds__(256) void k_stream_copy(const T *__restrict__ src, 
 template <typename T> void launch_copy(const void *src, void *dst, int64_t bytes, unsigned grid, hipStream_t s)
 {
     k_stream_copy<T><<<grid, 256, 0, s>>>((const T *)src, (T *)dst, bytes / (int64_t)sizeof(T));
+}
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+constexpr int kRateChains = 12;  // independent accumulators per wave, as in the direct sums
+
+// `iters` rounds of 12 independent v_mfma_f64_16x16x4f64 per wave; one wave
+// per SIMD per work-group of 256 threads.  Operands come from `in` (64 + 64
+// values) so that nothing folds; each thread writes one sum to out.
+__global__ __launch_bounds__(256) void k_mfma_f64_rate(const double *__restrict__ in, double *__restrict__ out,
+                                                       int iters)
+{
+    double a = in[threadIdx.x & 63];
+    const double b = in[64 + (threadIdx.x & 63)];
+    dx4 acc[kRateChains];
+#pragma unroll
+    for (int k = 0; k < kRateChains; ++k) acc[k] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < kRateChains; ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+        a = fma(a, 0.5, 0.25);  // stays near 0.5
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRateChains; ++k) sum += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
 }
 
 }  // namespace
@@ -91,5 +120,57 @@ extern "C" int bfsft_copy_rate(int elem_bytes, int64_t bytes, int reps, void *st
     if (e1) (void)hipEventDestroy(e1);
     if (a) (void)hipFree(a);
     if (b) (void)hipFree(b);
+    return rc;
+}
+
+extern "C" int bfsft_mfma_f64_rate(int waves_per_simd, int iters, void *stream, double *tflops)
+{
+    if (!tflops || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1 || iters > (1 << 20)) {
+        set_last_error("bfsft_mfma_f64_rate: waves_per_simd in [1, 8], iters in [1, 2^20], tflops not NULL");
+        return BFSFT_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || ncu < 1) {
+        set_last_error(std::string("bfsft_mfma_f64_rate: ") + hipGetErrorString(e));
+        return BFSFT_EDEVICE;
+    }
+    const int blocks = ncu * waves_per_simd;
+    double *buf = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = BFSFT_OK;
+    e = hipMalloc(&buf, sizeof(double) * (128 + (size_t)blocks * 256));
+    if (e != hipSuccess) {
+        set_last_error(std::string("bfsft_mfma_f64_rate: ") + hipGetErrorString(e));
+        return BFSFT_ENOMEM;
+    }
+    std::vector<double> ones(128, 1.0);
+    e = hipMemcpyAsync(buf, ones.data(), sizeof(double) * 128, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        k_mfma_f64_rate<<<blocks, 256, 0, s>>>(buf, buf + 128, std::min(iters, 64));  // untimed
+        e = hipEventRecord(e0, s);
+    }
+    if (e == hipSuccess) {
+        k_mfma_f64_rate<<<blocks, 256, 0, s>>>(buf, buf + 128, iters);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+        set_last_error(std::string("bfsft_mfma_f64_rate: ") + hipGetErrorString(e));
+        rc = BFSFT_EDEVICE;
+    } else {
+        // 4 waves per work-group, 12 MFMAs of 16 x 16 x 4 x 2 flops per round
+        *tflops = (double)blocks * 4.0 * iters * kRateChains * 2048.0 / (ms * 1e-3) / 1e12;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
     return rc;
 }

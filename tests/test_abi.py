@@ -96,3 +96,14 @@ def test_precision_values_match_the_boundary():
                     "BFSFT_MIXED": "4"}
     for name, code in bf.PRECISIONS.items():
         assert vals["BFSFT_" + name.upper()] == str(code)
+
+
+def test_measurement_helpers_reject_bad_arguments(lib):
+    # both helpers check their arguments before any device call
+    out = ctypes.c_double()
+    assert lib.bfsft_mfma_f64_rate(0, 10, None, ctypes.byref(out)) == -1
+    assert lib.bfsft_mfma_f64_rate(2, 0, None, ctypes.byref(out)) == -1
+    assert lib.bfsft_mfma_f64_rate(2, 10, None, None) == -1
+    assert lib.bfsft_copy_rate(3, 1 << 20, 1, None, ctypes.byref(out)) == -1
+    assert lib.bfsft_copy_rate(8, 1 << 10, 1, None, ctypes.byref(out)) == -1
+    assert lib.bfsft_last_error()

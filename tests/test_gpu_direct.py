@@ -127,3 +127,10 @@ def test_c2_full_size_start_5(bf, oracle_mod, monkeypatch):
     assert rel_l2(um[S], oracle_mod.direct(c2.x, c2.k, c2.f, c2.N, S)) <= 1e-6
     T = np.sort(np.random.default_rng(23).choice(c2.nx, 24, replace=False))
     assert rel_l2(um[T], oracle_u(oracle_mod, c2, 5, x=c2.x[T])) <= 1e-10
+
+
+def test_mfma_rate_helper(bf):
+    # the measurement helper the direct sums are compared with: a positive
+    # FP64 rate below the published matrix-core peak (78.6 TFLOP/s)
+    rate = bf.mfma_f64_rate(2, 4000)
+    assert 1.0 < rate < 80.0, rate
