@@ -499,7 +499,7 @@ StartChoice choose_start(const bfsft_plan *P)
     const double tr = (d == 2 ? 6.4e-4 : 1.54e-3) * std::pow(p, d + 1);
     const double dr = 0.0066 * (1.0 + 0.15 * (d - 2));
     const int pd = d == 2 ? P->p * P->p : P->p * P->p * P->p;
-    const int nt = (pd + 15) / 16;
+    const int nt = (pd % 16 == 1 && pd > 16) ? pd / 16 : (pd + 15) / 16;  // the kernel's column tiles
     const int maxc = nt <= 6 ? 8 : 4;
     auto direct_cost = [&](int l0, int s, int kind) {
         const double nk = (double)P->nk, nB = (double)P->tk.count[l0], nA = (double)P->tx.count[s];

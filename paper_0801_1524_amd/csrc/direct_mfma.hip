@@ -39,9 +39,12 @@ constexpr int kChunk = 16;  // sources of B per LDS chunk: four K-steps of 4
 
 template <int D, int P> struct DirectShape {
     static constexpr int PD = D == 2 ? P * P : P * P * P;  // grid points (columns)
-    static constexpr int NT = (PD + 15) / 16;                // 16-column tiles
-    static constexpr int NC = NT * 16;                       // padded columns
-    static constexpr int NR = PD / P;                        // column rows of P points: leading indices
+    // p^d = 16 k + 1 (p = 7, 9 in 2D): the last column is summed by the
+    // producers instead of padding a whole 16-column tile for it
+    static constexpr int XC = (PD % 16 == 1 && PD > 16) ? 1 : 0;
+    static constexpr int NT = XC ? PD / 16 : (PD + 15) / 16;  // 16-column tiles on the matrix cores
+    static constexpr int NC = NT * 16;                        // their columns
+    static constexpr int NR = PD / P;                         // column rows of P points: leading indices
 };
 
 template <int D, int P> constexpr bool mfma_shape_ok() { return DirectShape<D, P>::NT <= 9; }
@@ -92,7 +95,8 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
     using SH = DirectShape<D, P>;
     constexpr int PD = SH::PD, NT = SH::NT, NC = SH::NC, NR = SH::NR;
     constexpr int MAXC = max_consumers(NT);
-    constexpr int TS = NC + 1, GS = kChunk + 1;  // padded row strides (no bank conflicts)
+    constexpr int XC = SH::XC;
+    constexpr int TS = (XC ? PD : NC) + 1, GS = kChunk + 1;  // padded row strides (no bank conflicts)
     __shared__ double2 sT[2][kChunk][TS];
     __shared__ double2 sG[2][16 * MAXC][GS];
     __shared__ int4 s_desc[2];  // descriptor of the step held in each buffer
@@ -139,6 +143,7 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
             cre[nt] = dx4{0.0, 0.0, 0.0, 0.0};
             cim[nt] = dx4{0.0, 0.0, 0.0, 0.0};
         }
+        double2 xsum = make_double2(0.0, 0.0);  // last column (XC): this lane's sources of row i
         __syncthreads();  // step s_beg built
         for (int s = s_beg; s < s_end; ++s) {
             const int buf = (s - s_beg) & 1;
@@ -148,13 +153,18 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
                 const int nks = (count(d) + 3) >> 2;
                 const double2 *grow = &sG[buf][wave * 16 + i][0];
                 // operands of K-step ks into (g, bv); products of one K-step
-                auto fetch = [&](int ks, double2 &g, double2 (&bv)[NT]) {
+                // the last grid column (XC) rides along: its T entry with the
+                // operands, one complex FMA per K-step on the VALU
+                double2 xa = make_double2(0.0, 0.0), xta, xtb;
+                auto fetch = [&](int ks, double2 &g, double2 (&bv)[NT], double2 &xt) {
                     const int jr = ks * 4 + kq;
                     g = grow[jr];
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) bv[nt] = sT[buf][jr][nt * 16 + i];
+                    if (XC) xt = sT[buf][jr][PD - 1];
                 };
-                auto products = [&](const double2 &g, const double2 (&bv)[NT]) {
+                auto products = [&](const double2 &g, const double2 (&bv)[NT], const double2 &xt) {
+                    if (XC) cfma(xa, g, xt);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
                         cre[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, bv[nt].x, cre[nt], 0, 0, 0);
@@ -169,22 +179,37 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
                 // two operand sets in turn: the reads of K-step ks + 1 are
                 // issued before the products of K-step ks
                 double2 ga, gb, ba[NT], bb[NT];
-                fetch(0, ga, ba);
-                if (nks > 1) fetch(1, gb, bb);
+                fetch(0, ga, ba, xta);
+                if (nks > 1) fetch(1, gb, bb, xtb);
                 __builtin_amdgcn_sched_barrier(0);
-                products(ga, ba);
+                products(ga, ba, xta);
                 if (nks > 1) {
-                    if (nks > 2) fetch(2, ga, ba);
+                    if (nks > 2) fetch(2, ga, ba, xta);
                     __builtin_amdgcn_sched_barrier(0);
-                    products(gb, bb);
+                    products(gb, bb, xtb);
                 }
                 if (nks > 2) {
-                    if (nks > 3) fetch(3, gb, bb);
+                    if (nks > 3) fetch(3, gb, bb, xtb);
                     __builtin_amdgcn_sched_barrier(0);
-                    products(ga, ba);
+                    products(ga, ba, xta);
                 }
-                if (nks > 3) products(gb, bb);
+                if (nks > 3) products(gb, bb, xtb);
+                xsum = cadd(xsum, xa);
                 if ((d.y >> 9) & 1) {  // the item's last step: its potentials
+                    if (XC) {  // the last column: the four source lanes kq of row i
+                        xsum.x += __shfl_xor(xsum.x, 16);
+                        xsum.y += __shfl_xor(xsum.y, 16);
+                        xsum.x += __shfl_xor(xsum.x, 32);
+                        xsum.y += __shfl_xor(xsum.y, 32);
+                        const int ar = row0 + i;
+                        if (kq == 0 && ar < nA) {
+                            SV v;
+                            v.x = (S)xsum.x;
+                            v.y = (S)xsum.y;
+                            out[((int64_t)ar * nB + d.z) * PD + PD - 1] = v;
+                        }
+                        xsum = make_double2(0.0, 0.0);
+                    }
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
                         const int col = nt * 16 + i;
@@ -241,18 +266,18 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
     // this lane's source of a step: a valid source index whether or not j
     // is below the step's count (no branch around the loads)
     auto lane_src = [&](const int4 &q) { return q.x + min(j, max(count(q) - 1, 0)); };
-    auto decode = [&](const uint64_t (&key)[kRows], int64_t (&iA)[kRows][D]) {
+    auto decode = [&](const uint64_t (&key)[kRows], int (&iA)[kRows][D]) {
 #pragma unroll
         for (int k = 0; k < kRows; ++k)
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
-                int64_t v = 0;
-                for (int bit = 0; bit < dd.s0; ++bit) v |= (int64_t)((key[k] >> (bit * D + ax)) & 1) << bit;
+                int v = 0;  // below 2^s0 <= 2^18
+                for (int bit = 0; bit < dd.s0; ++bit) v |= (int)((key[k] >> (bit * D + ax)) & 1) << bit;
                 iA[k][ax] = v;
             }
     };
     // T rows and Gamma entries of one step into buffer buf
-    auto build = [&](int buf, const int4 &q, const SourceRegs<D> &r, const int64_t (&iA)[kRows][D]) {
+    auto build = [&](int buf, const int4 &q, const SourceRegs<D> &r, const int (&iA)[kRows][D]) {
         if (tp == 0) s_desc[buf] = q;
         const bool on = j < count(q);
         const double2 f = make_double2(r.fx, r.fy);
@@ -303,7 +328,7 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
     // of step s_beg + 2 and the descriptor of step s_beg + 3 in flight.
     // In the loop, dK is the raw descriptor of step s + K.
     int4 d1 = step(s_beg + 1), d2 = step(s_beg + 2), d3 = step(s_beg + 3);
-    int64_t iA[kRows][D];
+    int iA[kRows][D];
     uint64_t keys[kRows];
     {
         const int4 d0 = step(s_beg);
@@ -363,7 +388,8 @@ int direct_kinds(int d, int p)
 int direct_mfma_waves(int d, int p, int64_t nA)
 {
     const int pd = d == 2 ? p * p : p * p * p;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(max_consumers((pd + 15) / 16), (nA + 15) / 16));
+    const int nt = (pd % 16 == 1 && pd > 16) ? pd / 16 : (pd + 15) / 16;  // as DirectShape::NT
+    return (int)std::max<int64_t>(1, std::min<int64_t>(max_consumers(nt), (nA + 15) / 16));
 }
 
 template <typename F> void dispatch_direct(int d, int p, bool f32, F &&f)
