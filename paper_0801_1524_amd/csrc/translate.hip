@@ -85,6 +85,7 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                                       // bit 16 + 2*t2 + t1: some output with (t1, t2)
     __shared__ Cv s_sig[kRowsMax * 3];
     __shared__ signed char s_cj[kInMax * 8];
+    __shared__ Cv s_gc[4 * P];  // G(s, t, l) as [2 s][2 t][P]: stage 2 reads it at the lane's n
 
     const int64_t g = gid / a.ntile;
     const int tile = (int)(gid - g * a.ntile);
@@ -127,6 +128,8 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     __builtin_amdgcn_sched_barrier(0);
     Sv xn[P];
     load_row3(tid, xn);
+    const Cv gval = ldc<Cv>((cptr<C>)(a.C), min(tid, 4 * P - 1));  // clamped: no branch
+    if (tid < 4 * P) s_gc[tid] = gval;
     for (int bl = tid; bl < nb; bl += kTT) {  // nb <= kInMax < kTT: one pass
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -199,8 +202,8 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                 const int e0 = rem / P2;
                 const int ln = rem - e0 * P2;
                 const int l = ln / P, n = ln - l * P;
-                const Cv g0 = gcoef<Cv>(Ct, 0, t2, n, P);
-                Cv g1 = gcoef<Cv>(Ct, 1, t2, n, P);
+                const Cv g0 = s_gc[t2 * P + n];
+                Cv g1 = s_gc[(2 + t2) * P + n];
                 if (!RHO1) g1 = cmul(g1, sg2);
                 Cv z0[P], z1[P];
 #pragma unroll

@@ -91,6 +91,8 @@ template <typename Cv> struct Tables2D {
     int bits[kRowsMax];          // bit t: child t present; bit 4 + t2: a child with that t2
     Cv sig[kRowsMax * 2];        // [r][axis]: exp(2 pi i rho i_{A'}) (1 when rho = 1)
     signed char cj[kInMax * 4];  // [b][s]: local input index of child s of box b (or -1)
+    Cv gc[4 * kPMax2];           // G(s, t, l) as the table [2 s][2 t][P]: stage 2 reads it at
+                                 // the lane's column, which from LDS costs no memory latency
 };
 
 // What a thread loads ahead of an item's tables: the slot words of box
@@ -116,9 +118,11 @@ __device__ __forceinline__ Slots2D load_slots(const TArgs &a, const Item2D &it)
 
 // Fill the tables from the slot words (ends with a barrier; sets it.all).
 template <bool RHO1, typename Cv>
-__device__ __forceinline__ void fill_tables(const TArgs &a, Item2D &it, const Slots2D &h, Tables2D<Cv> &tb)
+__device__ __forceinline__ void fill_tables(const TArgs &a, Item2D &it, const Slots2D &h, Tables2D<Cv> &tb,
+                                            const Cv &gval, int ngc)
 {
     const int tid = threadIdx.x;
+    if (tid < ngc) tb.gc[tid] = gval;
     if (tid < it.nb) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -236,7 +240,7 @@ __device__ __forceinline__ void stage2_2d(const TArgs &a, const Item2D &it, cons
         const int c1 = tb.cj[bl * 4 + 1], c3 = tb.cj[bl * 4 + 3];
         // weights of the children at column m: G(s2, t2, m), sigma of
         // axis 2 with s2 = 1, sigma of axis 1 on the s1 = 1 sum
-        Cv g0 = gcoef<Cv>(Ct, 0, t2, m, P), g1 = gcoef<Cv>(Ct, 1, t2, m, P);
+        Cv g0 = tb.gc[t2 * P + m], g1 = tb.gc[(2 + t2) * P + m];
         if (!RHO1) g1 = cmul(g1, tb.sig[r * 2 + 1]);
         Cv h0 = g0, h1 = g1;
         if (!RHO1) {
@@ -292,7 +296,8 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the row's
     Sv xn[P];
     load_row<P>(a, it, threadIdx.x, xn);
-    fill_tables<RHO1>(a, it, h, tb);
+    const Cv gval = ldc<Cv>((cptr<C>)(a.C), min((int)threadIdx.x, 4 * P - 1));  // clamped: no branch
+    fill_tables<RHO1>(a, it, h, tb, gval, 4 * P);
     stage1_2d<P, S, C>(a, it, xn, Y, tb.bits);
     __syncthreads();
     stage2_2d<P, RHO1, S, C>(a, it, Y, tb);

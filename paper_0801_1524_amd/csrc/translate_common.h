@@ -18,6 +18,7 @@ constexpr int kTT = BFSFT_TT;  // threads of a translation work-group
 constexpr int kWaves = kTT / 64;
 constexpr int kRowsMax = 32;   // rows a' per work-group
 constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
+constexpr int kPMax2 = 12;     // largest 2D grid size p
 constexpr size_t kLdsMax = 60 * 1024;  // dynamic LDS of one work-group (static use stays below 4 KB)
 // Work-groups of one launch: its work-items (work-groups x kTT) must stay
 // below 2^32, or the dispatch runs only part of the grid.  Launches of more

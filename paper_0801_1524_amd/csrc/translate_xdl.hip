@@ -328,7 +328,8 @@ __device__ __forceinline__ void translate2d_xdl_item(const TArgs &a, int64_t gid
     float2 x[kBatch][XLane<P, F>::NE];
     load_batch<P, F>(a, it, 16 * (int)(threadIdx.x >> 6), it.R * it.nin * P, x);
     const XOp<P, F> op = make_op<P, F, C>(a);
-    fill_tables<RHO1>(a, it, h, tb);
+    const Cv gval = ldc<Cv>((cptr<C>)(a.C), min((int)threadIdx.x, 4 * P - 1));  // clamped: no branch
+    fill_tables<RHO1>(a, it, h, tb, gval, 4 * P);
     stage1_xdl<P, F>(a, it, x, Y, op);
     __syncthreads();
     stage2_2d<P, RHO1, float, C>(a, it, Y, tb);
