@@ -402,7 +402,9 @@ def main():
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.precisions is None:
-        args.precisions = "mixed,fp64,bf16x3" if args.workload == "c4" else "mixed,fp64,fp32,fp16x2,bf16x3"
+        # the split contraction formats (FP16X2, BF16X3) are 2D only
+        args.precisions = {"c4": "mixed,fp64,bf16x3", "c3": "mixed,fp64,fp32"}.get(
+            args.workload, "mixed,fp64,fp32,fp16x2,bf16x3")
     if args.summarize_counters:
         dirs = list(args.summarize_counters) + [None]
         summarize_counters(dirs[0], dirs[1], dirs[2], args.precisions.split(",")[0], COUNTERS)
