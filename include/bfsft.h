@@ -91,6 +91,8 @@ typedef struct {
                                              levels - start_level (0: at the leaves) */
     int start_kernel;                     /* single plan with start_level > 0: direct sums on
                                              0 the VALU, 1 the FP64 matrix cores */
+    int start_tables;                     /* 1: the matrix-core direct sums read plan-time
+                                             tables of their point-only factors */
 } bfsft_info;
 
 /*
@@ -129,6 +131,9 @@ typedef struct {
  * at the level of the method's error, not by rounding; the direct sums run
  * on the FP64 matrix cores (2D p <= 12, 3D p <= 5) or on the VALU
  * (BFSFT_DIRECT=valu forces the VALU kernel; the two differ by rounding);
+ * the matrix-core kernel reads plan-time tables of the factors that depend
+ * on the points only ((nA + p^d) x 16 bytes per source) when they fit
+ * BFSFT_DIRECT_TABLE_MB (default 2048; 0: computed at every execute);
  * BFSFT_TUNE_CACHE names the text file caching tuned choices (default
  * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget.
  */

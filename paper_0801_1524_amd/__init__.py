@@ -56,6 +56,7 @@ class Info(ctypes.Structure):
         ("level_kernel", ctypes.c_int * MAX_LEVELS), ("level_lds_kb", ctypes.c_int * MAX_LEVELS),
         ("start_level", ctypes.c_int),
         ("start_kernel", ctypes.c_int),
+        ("start_tables", ctypes.c_int),
     ]
 
 
@@ -202,6 +203,7 @@ def _info_dict(info: Info) -> dict:
         "level_kernel": list(info.level_kernel[:L]), "level_lds_kb": list(info.level_lds_kb[:L]),
         "start_level": info.start_level,
         "start_kernel": info.start_kernel,
+        "start_tables": info.start_tables,
     }
 
 

@@ -478,7 +478,8 @@ void build_tiles(bfsft_plan *P, int lds_bytes)
 // (pair, source, grid line), matrix-core direct sums per padded complex
 // multiply-add on the busiest SIMD (about 45 ns per FP64 MFMA with two
 // consumer waves per SIMD, a third more with one) plus the producers' work
-// per step (which the SIMD does not overlap with the products).  The
+// per step (which the SIMD does not overlap with the products; far less with
+// the plan-time tables of the point-only factors).  The
 // matrix-core kernel is taken in 3D and where at least 5 row tiles give two
 // consumer waves per SIMD; BFSFT_DIRECT restricts the choice.
 StartChoice choose_start(const bfsft_plan *P)
@@ -512,7 +513,13 @@ StartChoice choose_start(const bfsft_plan *P)
         const double load = simd_rows * (nk + 1.5 * nB) * 16.0 * nt;  // complex multiply-adds
         const double steps = blocks * (nk / 16.0 + 0.5 * nB);
         const double t_mfma = 45.0 * (d == 2 && w <= 4 ? 1.33 : 1.0);
-        return t_mfma * load / (256.0 * ncu) + steps / ncu * (350.0 * w + 300.0);
+        // the producers' work per step: loads and stores with the plan-time
+        // tables, the phases and chains without them
+        const double table_bytes = (nA * nk + nk * pd) * 16.0;
+        const bool tables = table_bytes <= (double)direct_table_budget() &&
+                            (P->arena.cap < 0 || (double)P->arena.bytes + table_bytes <= (double)P->arena.cap);
+        const double per_step = tables ? 200.0 * w + 300.0 : 450.0 * w + 300.0;
+        return t_mfma * load / (256.0 * ncu) + steps / ncu * per_step;
     };
     // the kernel at start level s: in 2D the matrix cores from 5 row tiles
     // on (with fewer, one consumer wave per SIMD, the VALU kernel measures
@@ -578,7 +585,7 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     P->start.kind = sc.kind;
     build_start(P->start, P->tk, sc.s0, P->d, P->p - 1, P->rho, P->arena, s);
     if (P->start.kind == 1 && P->start.s0 > 0)
-        build_direct_steps(P->start, P->tx, P->tk, P->d, P->p, P->arena, s);
+        build_direct_steps(P->start, P->tx, P->tk, P->tb, P->d, P->p, P->N, P->arena, s);
     build_tiles(P, translate_default_lds());
     BF_HIP(hipStreamSynchronize(s));
 }
@@ -626,7 +633,7 @@ bfsft_plan *make_adjoint(bfsft_plan *P)
             A->start.kind = sc.kind;
             build_start(A->start, A->tk, sc.s0, A->d, A->p - 1, A->rho, A->arena, A->stream);
             if (A->start.kind == 1 && A->start.s0 > 0)
-                build_direct_steps(A->start, A->tx, A->tk, A->d, A->p, A->arena, A->stream);
+                build_direct_steps(A->start, A->tx, A->tk, A->tb, A->d, A->p, A->N, A->arena, A->stream);
         }
         build_tiles(A, translate_default_lds());
         if (A->nx > 0 && A->nk > 0 && autotune_enabled()) autotune_single(A);
@@ -883,6 +890,7 @@ int bfsft_plan_info(const bfsft_plan *P, bfsft_info *o)
         o->lds_kb = P->lds / 1024;
         o->start_level = P->start.s0;
         o->start_kernel = P->start.s0 > 0 ? P->start.kind : 0;
+        o->start_tables = P->start.s0 > 0 && P->start.gam ? 1 : 0;
         for (int l = 0; l < P->L && l < (int)P->kind.size(); ++l) {
             o->level_kernel[l] = P->kind[l];
             o->level_lds_kb[l] = P->lds_level[l] / 1024;

@@ -183,6 +183,10 @@ struct StartLevel {
                                 //   z box b, w row block
     int32_t *wg_first = nullptr;// [nwg + 1] first step of every work-group
     int nwg = 0, nwaves = 0;
+    // matrix-core kernel, when they fit the table budget: the parts of the
+    // direct sums that depend on the points only, computed at plan time
+    double2 *gam = nullptr;     // [nA][npts] Gamma[A][j] (sources in sorted order)
+    double2 *geo = nullptr;     // [npts][p^d] T_j[l] / f_j
     int2 *box_leaf = nullptr;   // [count_K[L - s0]] leaf range of every box of T_K level L - s0
     int32_t *sm = nullptr;      // [npts][d] leaf index mod 2^s0 of every source (sorted order)
     double *sloc = nullptr;     // [npts][d] offset inside its leaf (sorted order)
@@ -200,6 +204,8 @@ void launch_direct(const Launch &c, const StartLevel &st, const double *f, const
 // unsupported).
 bool direct_mfma_supported(int d, int p);
 int direct_kinds(int d, int p);
+// byte budget of the matrix-core direct sums' plan-time tables
+int64_t direct_table_budget();
 
 // one transform of a (batched) direct start-level launch
 struct DirectDesc {
@@ -210,6 +216,8 @@ struct DirectDesc {
     const int4 *steps;          // matrix-core kernel only (single plans)
     const int32_t *wg_first;
     int nwg, nwaves;
+    const double2 *gam, *geo;   // matrix-core kernel: plan-time tables, or NULL
+    int64_t nk;                 // sources (row length of gam)
     const int32_t *leaf_beg;
     const int32_t *perm;
     const int32_t *sm;
@@ -225,8 +233,8 @@ DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, co
 int64_t direct_items(int d, int p, const DirectDesc &dd);
 void launch_direct_mfma(const Launch &c, const DirectDesc &dd);
 // the matrix-core kernel's step list for start level st.s0 (st.kind == 1)
-void build_direct_steps(StartLevel &st, const Tree &tx, const Tree &tk, int d, int p, Arena &arena,
-                        hipStream_t s);
+void build_direct_steps(StartLevel &st, const Tree &tx, const Tree &tk, const Tables &tb, int d, int p,
+                        int64_t N, Arena &arena, hipStream_t s);
 void launch_direct_batched(const Launch &c, const DirectDesc *ds, const int64_t *prefix, int n, int64_t total);
 
 // 2D translation with stage 1 on the matrix cores in the FP32, FP16X2 or

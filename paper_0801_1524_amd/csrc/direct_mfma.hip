@@ -89,7 +89,7 @@ constexpr int max_consumers(int nt) { return nt <= 6 ? 8 : 4; }
 // Operands of v_mfma_f64_16x16x4f64: lane i + 16 kq holds A[i][kq] and
 // B[kq][i]; register r of the result holds D[4 r + kq][i].  Here A = Gamma
 // (row i: A box, kq: source), B = T (kq: source, i: grid point).
-template <int D, int P, typename S>
+template <int D, int P, typename S, bool PRE>
 __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProducers), 1) void k_direct_mfma(DirectDesc dd)
 {
     using SH = DirectShape<D, P>;
@@ -237,6 +237,77 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
     const int tp = (int)threadIdx.x - 64 * W;  // 0 .. 255
     const int j = tp & 15, grp = tp >> 4;
     constexpr int kRows = MAXC;                 // Gamma rows per lane: grp + 16 k
+    // this lane's source of a step: a valid source index whether or not j
+    // is below the step's count (no branch around the loads)
+    auto lane_src = [&](const int4 &q) { return q.x + min(j, max(count(q) - 1, 0)); };
+
+    if constexpr (PRE) {
+        // Gamma and T / f from the plan-time tables: per step, loads, one
+        // complex multiply per T entry and stores only
+        constexpr int NRL = (NR + 15) / 16;  // T rows of this lane: grp, grp + 16
+        struct PreRegs {
+            double2 f;
+            double2 g[kRows];
+            double2 t[NRL][P];
+        };
+        const int64_t nk = dd.nk;
+        auto load_pre = [&](const int4 &q, int pidx, PreRegs &r) {
+            const int tt = lane_src(q);
+            r.f = dd.f[pidx];
+            const int base = q.w * 16 * W;
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) r.g[k] = dd.gam[(int64_t)min(base + grp + 16 * k, nA - 1) * nk + tt];
+#pragma unroll
+            for (int rr = 0; rr < NRL; ++rr) {
+                const double2 *src = dd.geo + (int64_t)tt * PD + min(grp + 16 * rr, NR - 1) * P;
+#pragma unroll
+                for (int l = 0; l < P; ++l) r.t[rr][l] = src[l];
+            }
+        };
+        auto build_pre = [&](int buf, const int4 &q, const PreRegs &r) {
+            if (tp == 0) s_desc[buf] = q;
+            const bool on = j < count(q);
+#pragma unroll
+            for (int rr = 0; rr < NRL; ++rr) {
+                const int row = grp + 16 * rr;
+                if (row >= NR) break;
+                double2 *dst = &sT[buf][j][row * P];
+#pragma unroll
+                for (int l = 0; l < P; ++l) dst[l] = on ? cmul(r.f, r.t[rr][l]) : make_double2(0.0, 0.0);
+            }
+            const int base = q.w * 16 * W;
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const int rr = grp + 16 * k;
+                if (rr >= 16 * W) break;
+                sG[buf][rr][j] = (on && base + rr < nA) ? r.g[k] : make_double2(0.0, 0.0);
+            }
+        };
+        int4 d1 = step(s_beg + 1), d2 = step(s_beg + 2), d3 = step(s_beg + 3);
+        PreRegs r;
+        {
+            const int4 d0 = step(s_beg);
+            load_pre(d0, dd.perm[lane_src(d0)], r);
+            build_pre(0, d0, r);
+        }
+        load_pre(d1, dd.perm[lane_src(d1)], r);
+        int pn = dd.perm[lane_src(d2)];
+        __syncthreads();
+        for (int s = s_beg; s < s_end; ++s) {
+            const int4 d4 = step(s + 4);
+            const int4 q1 = valid(d1, s + 1);
+            if (count(q1) > 0) build_pre((s + 1 - s_beg) & 1, q1, r);
+            // loads of step s + 2 and the source permutation of step s + 3
+            load_pre(d2, pn, r);
+            pn = dd.perm[lane_src(d3)];
+            d1 = d2;
+            d2 = d3;
+            d3 = d4;
+            __syncthreads();  // step s + 1 built; buffer of step s free
+        }
+        return;
+    }
+
     const int E = dd.s0 + dd.L;
     const uint64_t mask = (1ull << E) - 1ull;
     const double inv_2E = ldexp(1.0, -E), inv_2s0 = ldexp(1.0, -dd.s0);
@@ -263,9 +334,6 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
 #pragma unroll
         for (int k = 0; k < kRows; ++k) key[k] = dd.xkeys[min(blk * 16 * W + grp + 16 * k, nA - 1)];
     };
-    // this lane's source of a step: a valid source index whether or not j
-    // is below the step's count (no branch around the loads)
-    auto lane_src = [&](const int4 &q) { return q.x + min(j, max(count(q) - 1, 0)); };
     auto decode = [&](const uint64_t (&key)[kRows], int (&iA)[kRows][D]) {
 #pragma unroll
         for (int k = 0; k < kRows; ++k)
@@ -367,6 +435,61 @@ __global__ __launch_bounds__(64 * (max_consumers(DirectShape<D, P>::NT) + kProdu
     }
 }
 
+// Plan-time tables of the matrix-core direct sums (the parts that depend on
+// the points only; the same formulas the producers evaluate otherwise).
+// Gamma[a][t]: one thread per (A box a, source t in sorted order).
+template <int D>
+__global__ void k_gamma_table(int64_t nA, int64_t nk, int s0, int L, int64_t Nv, const uint64_t *__restrict__ xkeys,
+                              const int32_t *__restrict__ sm, const double *__restrict__ sloc,
+                              double2 *__restrict__ gam)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nA * nk) return;
+    const int64_t a = e / nk, t = e - a * nk;
+    const uint64_t key = xkeys[a];
+    const int E = s0 + L;
+    const uint64_t mask = (1ull << E) - 1ull, N = (uint64_t)Nv;
+    double th = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        uint64_t iA = 0;
+        for (int bit = 0; bit < s0; ++bit) iA |= ((key >> (bit * D + ax)) & 1ull) << bit;
+        const uint64_t red = (iA * (uint64_t)sm[t * D + ax] * N) & mask;
+        th += (double)red * ldexp(1.0, -E) + (double)iA * sloc[t * D + ax] * ldexp(1.0, -s0);
+    }
+    double sn, cs;
+    sincospi(2.0 * th, &sn, &cs);
+    gam[e] = make_double2(cs, sn);
+}
+
+// T_j[l] / f_j = prod_a (beta_a E[1])^{l_a}: one thread per (source t,
+// leading grid indices r), p entries along the last axis
+template <int D, int P>
+__global__ void k_geo_table(int64_t nk, const double2 *__restrict__ sstep, const double2 *__restrict__ erot,
+                            double2 *__restrict__ geo)
+{
+    constexpr int PD = D == 2 ? P * P : P * P * P, NR = PD / P;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nk * NR) return;
+    const int64_t t = e / NR;
+    const int r = (int)(e - t * NR);
+    const double2 e1 = erot[1];
+    double2 w = make_double2(1.0, 0.0);
+    if (D == 2) {
+        w = cpow_chain(cmul(sstep[t * D], e1), r);
+    } else {
+        const int l0 = r / P, l1 = r - l0 * P;
+        w = cmul(cpow_chain(cmul(sstep[t * D], e1), l0), cpow_chain(cmul(sstep[t * D + (D == 3 ? 1 : 0)], e1), l1));
+    }
+    const double2 bl = cmul(sstep[t * D + D - 1], e1);
+    double2 *dst = geo + t * PD + (int64_t)r * P;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        dst[l] = w;
+        w = cmul(w, bl);
+    }
+}
+
 }  // namespace
 
 bool direct_mfma_supported(int d, int p)
@@ -392,16 +515,16 @@ int direct_mfma_waves(int d, int p, int64_t nA)
     return (int)std::max<int64_t>(1, std::min<int64_t>(max_consumers(nt), (nA + 15) / 16));
 }
 
-template <typename F> void dispatch_direct(int d, int p, bool f32, F &&f)
+template <typename F> void dispatch_direct(int d, int p, bool f32, bool pre, F &&f)
 {
     auto go = [&](auto dim, auto tag) {
         constexpr int D = decltype(dim)::value;
         constexpr int Pc = decltype(tag)::value;
         if constexpr (mfma_shape_ok<D, Pc>()) {
             if (f32)
-                f(k_direct_mfma<D, Pc, float>);
+                pre ? f(k_direct_mfma<D, Pc, float, true>) : f(k_direct_mfma<D, Pc, float, false>);
             else
-                f(k_direct_mfma<D, Pc, double>);
+                pre ? f(k_direct_mfma<D, Pc, double, true>) : f(k_direct_mfma<D, Pc, double, false>);
         }
     };
     if (d == 2)
@@ -412,8 +535,21 @@ template <typename F> void dispatch_direct(int d, int p, bool f32, F &&f)
         });
 }
 
-void build_direct_steps(StartLevel &st, const Tree &tx, const Tree &tk, int d, int p, Arena &arena,
-                        hipStream_t s)
+// budget of the plan-time tables (BFSFT_DIRECT_TABLE_MB, default 2048 MB;
+// 0 disables them)
+int64_t direct_table_budget()
+{
+    int64_t mb = 2048;
+    if (const char *e = std::getenv("BFSFT_DIRECT_TABLE_MB")) {
+        char *end = nullptr;
+        const long long v = std::strtoll(e, &end, 10);
+        if (end != e && v >= 0) mb = v;
+    }
+    return mb << 20;
+}
+
+void build_direct_steps(StartLevel &st, const Tree &tx, const Tree &tk, const Tables &tb, int d, int p,
+                        int64_t N, Arena &arena, hipStream_t s)
 {
     if (!direct_mfma_supported(d, p)) throw Error{BFSFT_EINVAL, "matrix-core direct sums: unsupported (d, p)"};
     const int s0 = st.s0, L = tk.L, l0 = L - s0;
@@ -446,7 +582,36 @@ void build_direct_steps(StartLevel &st, const Tree &tx, const Tree &tk, int d, i
     int dev = 0, ncu = 0, per_cu = 0;
     BF_HIP(hipGetDevice(&dev));
     BF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    dispatch_direct(d, p, false, [&](auto kern) {
+    // plan-time tables when they fit the budget and the plan's byte cap
+    const int pd = d == 2 ? p * p : p * p * p;
+    const int64_t nk = tk.npts;
+    const int64_t table_bytes = (nA * nk + nk * pd) * (int64_t)sizeof(double2);
+    const bool pre = table_bytes <= direct_table_budget() &&
+                     (arena.cap < 0 || arena.bytes + table_bytes + (int64_t)(1 << 20) <= arena.cap);
+    if (pre) {
+        st.gam = (double2 *)arena.alloc(sizeof(double2) * (size_t)(nA * nk));
+        st.geo = (double2 *)arena.alloc(sizeof(double2) * (size_t)(nk * pd));
+        const int64_t ng = nA * nk;
+        const int64_t nr = nk * (pd / p);
+        const unsigned gg = (unsigned)((ng + 255) / 256), gr = (unsigned)((nr + 255) / 256);
+        const double2 *erot = (const double2 *)tb.erot;
+        if (d == 2)
+            k_gamma_table<2><<<gg, 256, 0, s>>>(nA, nk, s0, L, N, tx.keys[s0], st.sm, st.sloc, st.gam);
+        else
+            k_gamma_table<3><<<gg, 256, 0, s>>>(nA, nk, s0, L, N, tx.keys[s0], st.sm, st.sloc, st.gam);
+        auto geo = [&](auto dim, auto tag) {
+            constexpr int D = decltype(dim)::value, Pc = decltype(tag)::value;
+            k_geo_table<D, Pc><<<gr, 256, 0, s>>>(nk, st.sratio, erot, st.geo);
+        };
+        if (d == 2)
+            dispatch_p(p, [&](auto tag) { geo(std::integral_constant<int, 2>{}, tag); });
+        else
+            dispatch_p3(p, [&](auto tag) {
+                if constexpr (decltype(tag)::value <= 5) geo(std::integral_constant<int, 3>{}, tag);
+            });
+        BF_HIP(hipGetLastError());
+    }
+    dispatch_direct(d, p, false, pre, [&](auto kern) {
         BF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * (w + kProducers), 0));
     });
     const int64_t items = (int64_t)item_end.size();
@@ -479,7 +644,7 @@ void launch_direct_mfma(const Launch &c, const DirectDesc &dd)
     if (dd.nA == 0 || dd.nB == 0) return;
     if (!dd.steps || !dd.wg_first || dd.nwg < 1 || dd.nwaves < 1 || dd.nwaves > 8)
         throw Error{BFSFT_EINVAL, "matrix-core direct sums: no step list"};
-    dispatch_direct(c.d, c.p, c.precision != BFSFT_FP64, [&](auto kern) {
+    dispatch_direct(c.d, c.p, c.precision != BFSFT_FP64, dd.gam != nullptr, [&](auto kern) {
         kern<<<(unsigned)dd.nwg, 64 * (dd.nwaves + kProducers), 0, c.stream>>>(dd);
     });
     BF_HIP(hipGetLastError());

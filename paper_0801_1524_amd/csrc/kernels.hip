@@ -431,6 +431,8 @@ __device__ __forceinline__ DirectDesc load_direct_desc(const DirectDesc *descs, 
     d.steps = nullptr;
     d.wg_first = nullptr;
     d.nwg = d.nwaves = 0;
+    d.gam = d.geo = nullptr;
+    d.nk = 0;
     d.leaf_beg = p->leaf_beg;
     d.perm = p->perm;
     d.sm = p->sm;
@@ -693,6 +695,9 @@ DirectDesc direct_desc(const StartLevel &st, const double *f, const Tree &tx, co
     d.wg_first = st.wg_first;
     d.nwg = st.nwg;
     d.nwaves = st.nwaves;
+    d.gam = st.gam;
+    d.geo = st.geo;
+    d.nk = tk.npts;
     d.leaf_beg = tk.leaf_beg;
     d.perm = tk.perm;
     d.sm = st.sm;

@@ -134,3 +134,28 @@ def test_mfma_rate_helper(bf):
     # FP64 rate below the published matrix-core peak (78.6 TFLOP/s)
     rate = bf.mfma_f64_rate(2, 4000)
     assert 1.0 < rate < 80.0, rate
+
+
+@pytest.mark.parametrize("case", ["c1-3", "c1-5", "3d-3"])
+def test_plan_time_tables_on_and_off(bf, oracle_mod, monkeypatch, case):
+    """The matrix-core direct sums with their point-only factors from
+    plan-time tables (the default when they fit) and computed at every
+    execute (BFSFT_DIRECT_TABLE_MB=0): both against O2, and against each
+    other to rounding."""
+    if case.startswith("c1"):
+        P, start = synth.config("c1"), int(case[-1])
+    else:
+        N = 32
+        P = synth.Problem("s3", 3, N, 5, synth.sphere(N), synth.sphere(N, radius=0.3),
+                          synth.gaussian_sources(len(synth.sphere(N, radius=0.3)), 3))
+        start = 3
+    monkeypatch.setenv("BFSFT_DIRECT_TABLE_MB", "0")
+    u_off, i_off = run(bf, P, "fp64", start, "mfma", monkeypatch)
+    monkeypatch.delenv("BFSFT_DIRECT_TABLE_MB")
+    u_on, i_on = run(bf, P, "fp64", start, "mfma", monkeypatch)
+    assert i_off["start_kernel"] == 1 and i_off["start_tables"] == 0
+    assert i_on["start_kernel"] == 1 and i_on["start_tables"] == 1
+    ref = oracle_u(oracle_mod, P, i_on["start_level"])
+    assert rel_l2(u_on, ref) <= 1e-10
+    assert rel_l2(u_off, ref) <= 1e-10
+    assert rel_l2(u_on, u_off) <= 1e-13
