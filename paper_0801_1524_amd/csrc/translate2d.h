@@ -116,6 +116,23 @@ __device__ __forceinline__ Slots2D load_slots(const TArgs &a, const Item2D &it)
     return h;
 }
 
+// The G entry of thread tid (clamped, so the load is unconditional).
+template <int P, typename C>
+__device__ __forceinline__ typename CV<C>::t load_gc(const TArgs &a)
+{
+    return ldc<typename CV<C>::t>((cptr<C>)(a.C), min((int)threadIdx.x, 4 * P - 1));
+}
+
+// Marks v as used here.  Without it the compiler moves the load of an
+// entry that only some threads store into their branch, after the input
+// rows' loads; the wait for it there then waits for those rows too (the
+// counter of outstanding loads drains in order).  Placed after the rows'
+// loads are issued, the wait covers the entry's load alone.
+template <typename Cv> __device__ __forceinline__ void pin_after(Cv &v)
+{
+    asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
 // Fill the tables from the slot words (ends with a barrier; sets it.all).
 template <bool RHO1, typename Cv>
 __device__ __forceinline__ void fill_tables(const TArgs &a, Item2D &it, const Slots2D &h, Tables2D<Cv> &tb,
@@ -188,17 +205,32 @@ __device__ __forceinline__ void stage1_2d(const TArgs &a, const Item2D &it, type
     const int nrows = it.R * rowlen;
     const int ysz = it.R * it.nin * PP;  // one t2 half of Y
     const float inv_rowlen = 1.0f / (float)rowlen;
-    for (int v = threadIdx.x; v < nrows; v += kTT) {
+    auto row = [&](int v, const Cv *x) {
         const int r = (int)(((float)v + 0.5f) * inv_rowlen);
         const int w = v - r * rowlen;
         const int bits = s_bits[r];
+        Yv *Yr = Y + r * it.nin * PP + w * P;
+        if (bits & (1 << 4)) row_interp<P, 0, C>(Rt, x, Yr);
+        if (bits & (1 << 5)) row_interp<P, 1, C>(Rt, x, Yr + ysz);
+    };
+    if (nrows <= kTT) {
+        // at most one row per thread (uniform): no next row to load, so
+        // nothing is left in flight for the compiler to wait on before the
+        // barrier that follows
+        if ((int)threadIdx.x < nrows) {
+            Cv x[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
+            row(threadIdx.x, x);
+        }
+        return;
+    }
+    for (int v = threadIdx.x; v < nrows; v += kTT) {
         Cv x[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
         load_row<P>(a, it, v + kTT, xn);
-        Yv *Yr = Y + r * it.nin * PP + w * P;
-        if (bits & (1 << 4)) row_interp<P, 0, C>(Rt, x, Yr);
-        if (bits & (1 << 5)) row_interp<P, 1, C>(Rt, x, Yr + ysz);
+        row(v, x);
     }
 }
 
@@ -290,13 +322,15 @@ __device__ __forceinline__ void translate2d_item(const TArgs &a, int64_t gid, un
     __shared__ Tables2D<Cv> tb;
     Yv *Y = reinterpret_cast<Yv *>(smem);  // [2 t2][R][nin][P][P]
     Item2D it = item2d(a, gid);
-    // slot words first (the tables need them first), then the first input
-    // row, which stays in flight through the table fill and its barrier
+    // the G entry and the slot words first (the tables need them first),
+    // then the first input row, which stays in flight through the table
+    // fill and its barrier
+    Cv gval = load_gc<P, C>(a);
     const Slots2D h = load_slots(a, it);
     __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the row's
     Sv xn[P];
     load_row<P>(a, it, threadIdx.x, xn);
-    const Cv gval = ldc<Cv>((cptr<C>)(a.C), min((int)threadIdx.x, 4 * P - 1));  // clamped: no branch
+    pin_after(gval);
     fill_tables<RHO1>(a, it, h, tb, gval, 4 * P);
     stage1_2d<P, S, C>(a, it, xn, Y, tb.bits);
     __syncthreads();

@@ -322,13 +322,14 @@ __device__ __forceinline__ void translate2d_xdl_item(const TArgs &a, int64_t gid
     __shared__ Tables2D<Cv> tb;
     float2 *Y = reinterpret_cast<float2 *>(smem);  // [2 t2][R][nin][P][P]
     Item2D it = item2d(a, gid);
+    Cv gval = load_gc<P, C>(a);  // first: see pin_after
     const Slots2D h = load_slots(a, it);
     __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the lines'
     // the wave's first batch of lines, in flight through the table fill
     float2 x[kBatch][XLane<P, F>::NE];
     load_batch<P, F>(a, it, 16 * (int)(threadIdx.x >> 6), it.R * it.nin * P, x);
+    pin_after(gval);
     const XOp<P, F> op = make_op<P, F, C>(a);
-    const Cv gval = ldc<Cv>((cptr<C>)(a.C), min((int)threadIdx.x, 4 * P - 1));  // clamped: no branch
     fill_tables<RHO1>(a, it, h, tb, gval, 4 * P);
     stage1_xdl<P, F>(a, it, x, Y, op);
     __syncthreads();
