@@ -120,6 +120,7 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     // issued ahead of the first input row, which stays in flight through
     // the table fill and its barrier
     const int tid = threadIdx.x;
+    Cv gval = load_gc<P, C>(a);  // first: see pin_after
     const int bl_ = min(tid, nb - 1), r_ = min(tid, R - 1);
     const int kcb = a.k_cb[b0 + bl_];
     const uint64_t kw = a.k_slot[b0 + bl_];
@@ -128,7 +129,7 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     __builtin_amdgcn_sched_barrier(0);
     Sv xn[P];
     load_row3(tid, xn);
-    const Cv gval = ldc<Cv>((cptr<C>)(a.C), min(tid, 4 * P - 1));  // clamped: no branch
+    pin_after(gval);
     if (tid < 4 * P) s_gc[tid] = gval;
     for (int bl = tid; bl < nb; bl += kTT) {  // nb <= kInMax < kTT: one pass
 #pragma unroll
@@ -161,25 +162,41 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     const cptr<C> Rt = (cptr<C>)(a.R);
     const cptr<C> Ct = (cptr<C>)(a.C);
     bool first = true;  // xn holds the thread's first row
+    // unrolled: each position t2 gets its own registers for the rows, so no
+    // copy (and no wait for a load in flight) joins the two passes
+#pragma unroll
     for (int t2 = 0; t2 < 2; ++t2) {
         if (!(all & (1 << (8 + t2)))) continue;  // uniform
-        // stage 1: rows of the rows a' that need t2
-        if (!first) load_row3(tid, xn);
+        // stage 1: rows of the rows a' that need t2 (with one row per
+        // thread, xn still holds it from the first position)
+        if (!first && nrows > kTT) load_row3(tid, xn);
         first = false;
-        for (int v = tid; v < nrows; v += kTT) {
+        auto row = [&](int v, const Cv *x) {
             const int r = (int)(((float)v + 0.5f) * inv_rowlen);
             const int w = v - r * rowlen;
-            const bool need = (s_bits[r] >> (8 + t2)) & 1;
-            Cv x[P];
-#pragma unroll
-            for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
-            load_row3(v + kTT, xn);
-            if (!need) continue;
+            if (!((s_bits[r] >> (8 + t2)) & 1)) return;
             Yv *dst = Y1 + r * rowlen * P + w * P;
             if (t2 == 0)
                 row_interp<P, 0, C>(Rt, x, dst);
             else
                 row_interp<P, 1, C>(Rt, x, dst);
+        };
+        if (nrows <= kTT) {
+            // at most one row per thread (uniform): no next row to load
+            if (tid < nrows) {
+                Cv x[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
+                row(tid, x);
+            }
+        } else {
+            for (int v = tid; v < nrows; v += kTT) {
+                Cv x[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) x[m] = cvt<Cv>(xn[m]);
+                load_row3(v + kTT, xn);
+                row(v, x);
+            }
         }
         __syncthreads();
         for (int pass = 0; pass < 2 / NT1; ++pass) {
