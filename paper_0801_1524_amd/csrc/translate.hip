@@ -84,7 +84,7 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
     __shared__ int s_bits[kRowsMax];  // bit t: output t; bit 8+t2: some output with t2;
                                       // bit 16 + 2*t2 + t1: some output with (t1, t2)
     __shared__ Cv s_sig[kRowsMax * 3];
-    __shared__ signed char s_cj[kInMax * 8];
+    __shared__ __align__(8) signed char s_cj[kInMax * 8];  // read as one 64-bit word per box
     __shared__ Cv s_gc[4 * P];  // G(s, t, l) as [2 s][2 t][P]: stage 2 reads it at the lane's n
 
     const int64_t g = gid / a.ntile;
@@ -225,18 +225,25 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                 Cv z0[P], z1[P];
 #pragma unroll
                 for (int m = 0; m < P; ++m) z0[m] = z1[m] = czero<Cv>();
+                // the box's eight child slots in one read; a child's line is
+                // read whole before it is used (one LDS wait per child)
+                const uint64_t cw = *reinterpret_cast<const uint64_t *>(s_cj + bl * 8);
 #pragma unroll
                 for (int e12 = 0; e12 < 4; ++e12) {  // e1 = bit 0 of e12, e2 = bit 1
-                    const int c = s_cj[bl * 8 + e0 + 2 * e12];
+                    const int c = (int)(signed char)((cw >> (8 * (e0 + 2 * e12))) & 0xffu);
                     if (c < 0) continue;
                     const Cv gw = (e12 & 2) ? g1 : g0;
                     const Yv *yp = Yr + c * P3 + l * P2 + n;
+                    Yv y[P];
+#pragma unroll
+                    for (int m = 0; m < P; ++m) y[m] = yp[m * P];
+                    __builtin_amdgcn_sched_barrier(0);
                     if (e12 & 1) {
 #pragma unroll
-                        for (int m = 0; m < P; ++m) cfma(z1[m], gw, ld<Cv>(yp + m * P));
+                        for (int m = 0; m < P; ++m) cfma(z1[m], gw, cvt<Cv>(y[m]));
                     } else {
 #pragma unroll
-                        for (int m = 0; m < P; ++m) cfma(z0[m], gw, ld<Cv>(yp + m * P));
+                        for (int m = 0; m < P; ++m) cfma(z0[m], gw, cvt<Cv>(y[m]));
                     }
                 }
                 if (!RHO1) {
@@ -275,14 +282,23 @@ __device__ __forceinline__ void translate3d_item(const TArgs &a, int64_t gid, un
                 Cv z0[P], z1[P];
                 const Yv *y0 = Y2r + ((bl * NT1 + k) * 2 + 0) * P3 + mn;
                 const Yv *y1 = y0 + P3;
-                const bool h1 = (s_cj[bl * 8 + 1] >= 0) | (s_cj[bl * 8 + 3] >= 0) |
-                                (s_cj[bl * 8 + 5] >= 0) | (s_cj[bl * 8 + 7] >= 0);
-                const bool h0 = (s_cj[bl * 8 + 0] >= 0) | (s_cj[bl * 8 + 2] >= 0) |
-                                (s_cj[bl * 8 + 4] >= 0) | (s_cj[bl * 8 + 6] >= 0);
+                // a child slot is present when its byte is >= 0 (sign bit clear)
+                const uint64_t cw = *reinterpret_cast<const uint64_t *>(s_cj + bl * 8);
+                const bool h1 = (~cw & 0x8000800080008000ull) != 0;  // slots 1, 3, 5, 7
+                const bool h0 = (~cw & 0x0080008000800080ull) != 0;  // slots 0, 2, 4, 6
+                // both lines read whole first (in the tile's Y2 whatever the
+                // flags: one LDS wait), absent halves then taken as zero
+                Yv v0[P], v1[P];
 #pragma unroll
                 for (int l = 0; l < P; ++l) {
-                    z0[l] = h0 ? ld<Cv>(y0 + l * P2) : czero<Cv>();
-                    z1[l] = h1 ? ld<Cv>(y1 + l * P2) : czero<Cv>();
+                    v0[l] = y0[l * P2];
+                    v1[l] = y1[l * P2];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    z0[l] = h0 ? cvt<Cv>(v0[l]) : czero<Cv>();
+                    z1[l] = h1 ? cvt<Cv>(v1[l]) : czero<Cv>();
                     if (!RHO1) z1[l] = cmul(z1[l], sg0);
                 }
                 if (a0 >= 0)

@@ -280,29 +280,41 @@ __device__ __forceinline__ void stage2_2d(const TArgs &a, const Item2D &it, cons
             h0 = cmul(h0, sg);
             h1 = cmul(h1, sg);
         }
-        // one branch per child slot, not per element
+        // one branch per child slot, not per element; a child's column is
+        // read whole before it is used, so its reads wait on LDS once
+        // (interleaved, each read waited for the previous one's use)
+        auto column = [&](int c, Yv *v) {
+            const Yv *yp = Yr + c * PP + m;
+#pragma unroll
+            for (int l = 0; l < P; ++l) v[l] = yp[l * P];
+            __builtin_amdgcn_sched_barrier(0);
+        };
         Cv z0[P], z1[P];
 #pragma unroll
         for (int l = 0; l < P; ++l) z0[l] = z1[l] = czero<Cv>();
         if (c0 >= 0) {
-            const Yv *yp = Yr + c0 * PP + m;
+            Yv v[P];
+            column(c0, v);
 #pragma unroll
-            for (int l = 0; l < P; ++l) z0[l] = cmul(g0, ld<Cv>(yp + l * P));
+            for (int l = 0; l < P; ++l) z0[l] = cmul(g0, cvt<Cv>(v[l]));
         }
         if (c2 >= 0) {
-            const Yv *yp = Yr + c2 * PP + m;
+            Yv v[P];
+            column(c2, v);
 #pragma unroll
-            for (int l = 0; l < P; ++l) cfma(z0[l], g1, ld<Cv>(yp + l * P));
+            for (int l = 0; l < P; ++l) cfma(z0[l], g1, cvt<Cv>(v[l]));
         }
         if (c1 >= 0) {
-            const Yv *yp = Yr + c1 * PP + m;
+            Yv v[P];
+            column(c1, v);
 #pragma unroll
-            for (int l = 0; l < P; ++l) z1[l] = cmul(h0, ld<Cv>(yp + l * P));
+            for (int l = 0; l < P; ++l) z1[l] = cmul(h0, cvt<Cv>(v[l]));
         }
         if (c3 >= 0) {
-            const Yv *yp = Yr + c3 * PP + m;
+            Yv v[P];
+            column(c3, v);
 #pragma unroll
-            for (int l = 0; l < P; ++l) cfma(z1[l], h1, ld<Cv>(yp + l * P));
+            for (int l = 0; l < P; ++l) cfma(z1[l], h1, cvt<Cv>(v[l]));
         }
         Sv *o0 = reinterpret_cast<Sv *>(a.out) + ((int64_t)a0 * a.out_row + b0 + bl) * PP + m;
         Sv *o1 = reinterpret_cast<Sv *>(a.out) + ((int64_t)a1 * a.out_row + b0 + bl) * PP + m;
