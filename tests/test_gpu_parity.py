@@ -132,6 +132,32 @@ def test_chunked_launches_match_one_launch(bf, monkeypatch, d, kernel):
     assert np.array_equal(u_one, u_chunked)
 
 
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tile_budgets_one_and_several_rows_per_thread(bf, oracle_mod, monkeypatch, d, precision):
+    """Untuned tiles at the smallest and the largest LDS budget.  At 8 KB a
+    tile's stage 1 has at most one input row per thread (no next row is
+    loaded); at 60 KB several (the next row is loaded while the current one
+    is computed, and in 3D the rows are loaded again for the second axis-2
+    position).  Both against O2, and against each other: the arithmetic of
+    an output does not depend on the tile, so they agree to rounding."""
+    if d == 2:
+        P, case = synth.config("c1"), "c1"
+    else:
+        x = synth.sphere(32)
+        P = synth.Problem("sph32", 3, 32, 5, x, x.copy(), synth.gaussian_sources(x.shape[0], 3))
+        case = "sph32p5"
+    monkeypatch.setenv("BFSFT_AUTOTUNE", "0")
+    ref = oracle_u(oracle_mod, P)
+    us = []
+    for kb in ("8", "60"):
+        monkeypatch.setenv("BFSFT_LDS_KB", kb)
+        u = gpu_u(bf, P, precision)
+        check_o2(rel_l2(u, ref), case, precision)
+        us.append(u)
+    assert rel_l2(us[0], us[1]) <= 1e-14
+
+
 def test_deterministic(bf):
     P = synth.config("c1")
     with bf.Plan(P.d, P.N, P.p, P.x, P.k, "fp64") as plan:
