@@ -477,25 +477,46 @@ __device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *
 {
     if (i >= nx) return;
     constexpr int q = P - 1;
+    // exp(i pi node_turns[k]) for every node, by recurrence from the first
+    // (node_turns[k] is k node_turns[1] up to one rounding; the products
+    // drift by a few ulps at most), shared by the axes
+    double2 nph[P];
+    {
+        double s, c;
+        sincospi(node_turns[1], &s, &c);
+        nph[0] = make_double2(1.0, 0.0);
+#pragma unroll
+        for (int k = 1; k < P; ++k) nph[k] = cmul(nph[k - 1], make_double2(c, s));
+    }
     double2 ell[D][P];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const double xt = local[i * D + a] / (double)q;  // turns of z = exp(2 pi i x'/q)
+        double sx, cx;
+        sincospi(xt, &sx, &cx);
         int exact = -1;
         double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
         for (int k = 0; k < P; ++k) {
+            // z - z_k = 2 i sin(pi (xt - t_k)) e with e = exp(i pi (xt + t_k)),
+            // |e| = 1, so 1 / (z - z_k) = -i conj(e) / (2 sin(pi (xt - t_k))):
+            // the difference of the turns is taken exactly (no cancellation
+            // between close points), and one real division per node
             const double amb = xt - node_turns[k];
-            if (amb == 0.0) exact = k;
-            const double2 w = ddiv(bary[k], diff_unit(amb, xt + node_turns[k]));
+            if (amb == 0.0) exact = k;  // that node's weight is replaced below
+            const double2 e = cmul(make_double2(cx, sx), nph[k]);
+            const double h = 0.5 / sinpi(amb);
+            const double2 w = cmul(bary[k], make_double2(-e.y * h, -e.x * h));
             ell[a][k] = w;
             sum.x += w.x;
             sum.y += w.y;
         }
+        const double n2 = sum.x * sum.x + sum.y * sum.y;
+        const double2 rs = make_double2(sum.x / n2, -sum.y / n2);  // 1 / sum
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const double2 e = make_double2(erot[k].x, -erot[k].y);
-            ell[a][k] = exact >= 0 ? (k == exact ? e : make_double2(0.0, 0.0)) : cmul(ddiv(ell[a][k], sum), e);
+            ell[a][k] = exact >= 0 ? (k == exact ? e : make_double2(0.0, 0.0)) : cmul(cmul(ell[a][k], rs), e);
         }
     }
     constexpr int PD = (D == 2) ? P * P : P * P * P;
