@@ -487,7 +487,7 @@ void launch_translate(const Launch &c, const LevelArgs &la)
     if (grid == 0) return;
     const TArgs a = make_targs(c, la);
     const size_t lds = translate_lds_bytes(c.d, c.p, c.precision, la.rows, la.cost_max);
-    if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
+    if (lds > (c.d == 2 ? kLdsMax2D : kLdsMax)) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
     auto body = [&](auto tag, auto *sp, auto *cp, auto d3) {
         constexpr int P = decltype(tag)::value;
         using S = std::remove_pointer_t<decltype(sp)>;

@@ -20,6 +20,10 @@ constexpr int kRowsMax = 32;   // rows a' per work-group
 constexpr int kInMax = 127;    // inputs of a tile (local child indices fit a signed char)
 constexpr int kPMax2 = 12;     // largest 2D grid size p
 constexpr size_t kLdsMax = 60 * 1024;  // dynamic LDS of one work-group (static use stays below 4 KB)
+// 2D single-transform tiles may be larger: two work-groups of this size and
+// their static tables still fit the 160 KB of a CU (for the last levels,
+// whose rows hold few boxes, so a tile needs many rows to fill stage 2)
+constexpr size_t kLdsMax2D = 76 * 1024;
 // Work-groups of one launch: its work-items (work-groups x kTT) must stay
 // below 2^32, or the dispatch runs only part of the grid.  Launches of more
 // work items are split into chunks of this many, each told its first item.

@@ -395,7 +395,7 @@ void launch_translate_mfma(const Launch &c, const LevelArgs &la)
     if (grid == 0) return;
     const TArgs a = make_targs(c, la);
     const size_t lds = translate_lds_bytes(2, c.p, c.precision, la.rows, la.cost_max, 1);
-    if (lds > kLdsMax) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
+    if (lds > kLdsMax2D) throw Error{BFSFT_EINVAL, "translation tile exceeds LDS"};
     dispatch_p59(c.p, [&](auto tag) {
         constexpr int P = decltype(tag)::value;
         // chunks of at most kMaxGroups work-groups (see kMaxGroups)
