@@ -244,20 +244,14 @@ def time_precision(bf, torch, P, precision, steps, warmup):
     u = torch.empty(P.nx, dtype=torch.complex128, device="cuda")
     for _ in range(warmup):
         plan.execute(f, out=u)
-    # the timed steps record no events (an event between two launches
-    # holds the next one back by a few microseconds) ...
+    torch.cuda.synchronize()
+    plan.timing_begin(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         plan.execute(f, out=u)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # ... the per-kernel breakdown comes from as many steps again, with
-    # HIP events around every launch on the plan's stream
-    plan.timing_begin(steps)
-    for i in range(steps):
-        plan.execute(f, out=u)
-    torch.cuda.synchronize()
     tm = plan.timing_end()
     info = plan.info()
     out = u.cpu().numpy()
