@@ -369,8 +369,9 @@ void run(bfsft_plan *P, const double *f, double *u, int probe_level, double *pot
     if (probe_level == l0)
         launch_export(c, B[0], P->tx.keys[s0], P->tx.count[s0], P->tk.keys[l0], P->tk.count[l0], l0, L,
                       P->N, pot);
-    if (ev)  // levels above the start have no translation: zero-length intervals
-        for (int l = L - 1; l >= l0; --l) BF_HIP(hipEventRecord(ev[2 + (L - 1 - l)], P->stream));
+    // levels above the start have no translation and record no event (each
+    // event between two launches delays the next by a few microseconds);
+    // bfsft_timing_end reports zero for them
     int cur = 0;
     for (int l = l0 - 1; l >= 0; --l) {
         launch_translate(c, level_args(P, l, B[cur], B[cur ^ 1]));
@@ -843,17 +844,22 @@ int bfsft_timing_end(bfsft_plan *P, double *out, int n)
         const int L = P->L;
         for (int i = 0; i < n; ++i) out[i] = 0.0;
         out[0] = P->tcount;
+        // events: 0 start, 1 after the leaf or direct sums, 2 + (L - 1 - l)
+        // after translation level l (only l < l0, the translated levels),
+        // L + 2 after the final evaluation
+        const int l0 = L - P->start.s0;
         for (int r = 0; r < P->tcount; ++r) {
             hipEvent_t *ev = &P->tev[(size_t)r * (L + 3)];
             BF_HIP(hipEventSynchronize(ev[L + 2]));
             float ms = 0.f;
             BF_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
             out[1] += ms;
-            BF_HIP(hipEventElapsedTime(&ms, ev[L + 1], ev[L + 2]));
+            BF_HIP(hipEventElapsedTime(&ms, l0 > 0 ? ev[L + 1] : ev[1], ev[L + 2]));
             out[2] += ms;
-            for (int i = 0; i < L; ++i) {
-                BF_HIP(hipEventElapsedTime(&ms, ev[1 + i], ev[2 + i]));
-                out[3 + (L - 1 - i)] += ms;
+            for (int l = l0 - 1; l >= 0; --l) {
+                const hipEvent_t before = l == l0 - 1 ? ev[1] : ev[2 + (L - 1 - (l + 1))];
+                BF_HIP(hipEventElapsedTime(&ms, before, ev[2 + (L - 1 - l)]));
+                out[3 + l] += ms;
             }
         }
         free_events(P);

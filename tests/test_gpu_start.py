@@ -208,3 +208,32 @@ def test_largest_N(bf, oracle_mod, monkeypatch, d, N, p, n, precision, start):
     if precision == "fp64":
         T = np.arange(0, P.nx, 40 if d == 2 else 25)
         assert rel_l2(u[T], oracle_u(oracle_mod, P, s0, x=P.x[T])) <= 1e-10
+
+
+@pytest.mark.parametrize("start", ["chosen", "0", "12"])
+def test_timing_intervals(bf, monkeypatch, start):
+    """The per-launch event intervals (what bench.py reports per level):
+    positive for the translated levels below the start, zero for the levels
+    above it (which record no event), positive for the start and the final
+    evaluation; C1 has 12 levels, so start 12 translates nothing."""
+    if start == "chosen":
+        monkeypatch.delenv("BFSFT_START_LEVEL", raising=False)
+    else:
+        monkeypatch.setenv("BFSFT_START_LEVEL", start)
+    P = synth.config("c1")
+    with bf.Plan(P.d, P.N, P.p, P.x, P.k, "mixed") as plan:
+        plan.timing_begin(3)
+        for _ in range(3):
+            plan.execute(P.f)
+        tm = plan.timing_end()
+        inf = plan.info()
+    L, s0 = inf["levels"], inf["start_level"]
+    if start != "chosen":
+        assert s0 == int(start)
+    assert tm["executes"] == 3
+    assert tm["leaf_ms"] > 0 and tm["final_ms"] > 0
+    for l in range(L):
+        if l < L - s0:
+            assert tm["translate_ms"][l] > 0, l
+        else:
+            assert tm["translate_ms"][l] == 0, l
