@@ -466,6 +466,60 @@ __global__ __launch_bounds__(256, (direct_waves<P>())) void k_direct_batched(con
 // Step 4: u_i = sum_l prod_a ell_{l_a}(exp(2 pi i x'_{i,a} / q)) w^{A B0}_l for
 // x_i in leaf A of T_X (barycentric Lagrange interpolation); the state is
 // rotated, w = conj(E x ... x E) w^, so each weight takes conj(E[l_a]).
+
+// exp(i pi node_turns[k]) for every node, by recurrence from the first
+// (node_turns[k] is k node_turns[1] up to one rounding; the products drift
+// by a few ulps at most)
+template <int P>
+__device__ __forceinline__ void node_phases(const double *__restrict__ node_turns, double2 *nph)
+{
+    double s, c;
+    sincospi(node_turns[1], &s, &c);
+    nph[0] = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int k = 1; k < P; ++k) nph[k] = cmul(nph[k - 1], make_double2(c, s));
+}
+
+// The P weights of one axis at xt turns of z = exp(2 pi i x'/q), each times
+// conj(E[k]); a point on a node takes that node's E alone.
+template <int P>
+__device__ __forceinline__ void axis_weights(double xt, const double2 *__restrict__ bary,
+                                             const double *__restrict__ node_turns,
+                                             const double2 *__restrict__ erot, const double2 *nph, double2 *ell)
+{
+    double sx, cx;
+    sincospi(xt, &sx, &cx);
+    int exact = -1;
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        // z - z_k = 2 i sin(pi (xt - t_k)) e with e = exp(i pi (xt + t_k)),
+        // |e| = 1, so 1 / (z - z_k) = -i conj(e) / (2 sin(pi (xt - t_k))):
+        // the difference of the turns is taken exactly (no cancellation
+        // between close points), and one real division per node
+        const double amb = xt - node_turns[k];
+        if (amb == 0.0) exact = k;  // that node's weight is replaced below
+        const double2 e = cmul(make_double2(cx, sx), nph[k]);
+        const double h = 0.5 / sinpi(amb);
+        const double2 w = cmul(bary[k], make_double2(-e.y * h, -e.x * h));
+        ell[k] = w;
+        sum.x += w.x;
+        sum.y += w.y;
+    }
+    const double n2 = sum.x * sum.x + sum.y * sum.y;
+    const double2 rs = make_double2(sum.x / n2, -sum.y / n2);  // 1 / sum
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const double2 e = make_double2(erot[k].x, -erot[k].y);
+        ell[k] = exact >= 0 ? (k == exact ? e : make_double2(0.0, 0.0)) : cmul(cmul(ell[k], rs), e);
+    }
+}
+
+// rows of the 2D sum taken by the first lane of a pair (k_final2); the
+// one-lane form sums the same two halves in the same order, so both give
+// the same bits
+template <int P> constexpr int final_half() { return (P + 1) / 2; }
+
 template <int D, int P, typename S>
 __device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *__restrict__ state,
                                            const int32_t *__restrict__ leaf_of,
@@ -477,59 +531,25 @@ __device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *
 {
     if (i >= nx) return;
     constexpr int q = P - 1;
-    // exp(i pi node_turns[k]) for every node, by recurrence from the first
-    // (node_turns[k] is k node_turns[1] up to one rounding; the products
-    // drift by a few ulps at most), shared by the axes
     double2 nph[P];
-    {
-        double s, c;
-        sincospi(node_turns[1], &s, &c);
-        nph[0] = make_double2(1.0, 0.0);
-#pragma unroll
-        for (int k = 1; k < P; ++k) nph[k] = cmul(nph[k - 1], make_double2(c, s));
-    }
+    node_phases<P>(node_turns, nph);
     double2 ell[D][P];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        const double xt = local[i * D + a] / (double)q;  // turns of z = exp(2 pi i x'/q)
-        double sx, cx;
-        sincospi(xt, &sx, &cx);
-        int exact = -1;
-        double2 sum = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            // z - z_k = 2 i sin(pi (xt - t_k)) e with e = exp(i pi (xt + t_k)),
-            // |e| = 1, so 1 / (z - z_k) = -i conj(e) / (2 sin(pi (xt - t_k))):
-            // the difference of the turns is taken exactly (no cancellation
-            // between close points), and one real division per node
-            const double amb = xt - node_turns[k];
-            if (amb == 0.0) exact = k;  // that node's weight is replaced below
-            const double2 e = cmul(make_double2(cx, sx), nph[k]);
-            const double h = 0.5 / sinpi(amb);
-            const double2 w = cmul(bary[k], make_double2(-e.y * h, -e.x * h));
-            ell[a][k] = w;
-            sum.x += w.x;
-            sum.y += w.y;
-        }
-        const double n2 = sum.x * sum.x + sum.y * sum.y;
-        const double2 rs = make_double2(sum.x / n2, -sum.y / n2);  // 1 / sum
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const double2 e = make_double2(erot[k].x, -erot[k].y);
-            ell[a][k] = exact >= 0 ? (k == exact ? e : make_double2(0.0, 0.0)) : cmul(cmul(ell[a][k], rs), e);
-        }
-    }
+    for (int a = 0; a < D; ++a) axis_weights<P>(local[i * D + a] / (double)q, bary, node_turns, erot, nph, ell[a]);
     constexpr int PD = (D == 2) ? P * P : P * P * P;
     const typename CV<S>::t *w = state + (int64_t)leaf_of[i] * PD;
     double2 acc = make_double2(0.0, 0.0);
     if (D == 2) {
+        constexpr int LH = final_half<P>();
+        double2 half[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
 #pragma unroll
         for (int l = 0; l < P; ++l) {
             double2 r = make_double2(0.0, 0.0);
 #pragma unroll
             for (int m = 0; m < P; ++m) cfma(r, ell[1][m], cvt<double2>(w[l * P + m]));
-            cfma(acc, ell[0][l], r);
+            cfma(half[l >= LH], ell[0][l], r);
         }
+        acc = make_double2(half[0].x + half[1].x, half[0].y + half[1].y);
     } else {
 #pragma unroll
         for (int l = 0; l < P; ++l) {
@@ -544,6 +564,52 @@ __device__ __forceinline__ void final_item(int64_t nx, const typename CV<S>::t *
         }
     }
     u[i] = acc;
+}
+
+// 2D with two lanes per target: lane a of the pair computes the weights of
+// axis a (the pair exchanges them) and half of the rows l of the sum; the
+// halves are added as in final_item.
+template <int P, typename S>
+__global__ __launch_bounds__(256) void k_final2(int64_t nx, const typename CV<S>::t *__restrict__ state,
+                                               const int32_t *__restrict__ leaf_of,
+                                               const double *__restrict__ local,
+                                               const double2 *__restrict__ bary,
+                                               const double *__restrict__ node_turns,
+                                               const double2 *__restrict__ erot,
+                                               double2 *__restrict__ u)
+{
+    constexpr int q = P - 1, LH = final_half<P>();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = g >> 1;
+    const int a = (int)(g & 1);
+    // clamped, so that both lanes of every pair run the exchanges below
+    const int64_t i = i0 < nx ? i0 : nx - 1;
+    double2 nph[P];
+    node_phases<P>(node_turns, nph);
+    double2 own[P];
+    axis_weights<P>(local[i * 2 + a] / (double)q, bary, node_turns, erot, nph, own);
+    double2 e0[P], e1[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const double2 o = make_double2(__shfl_xor(own[k].x, 1), __shfl_xor(own[k].y, 1));
+        e0[k] = a ? o : own[k];
+        e1[k] = a ? own[k] : o;
+    }
+    const typename CV<S>::t *w = state + (int64_t)leaf_of[i] * (P * P);
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < LH; ++k) {
+        const int l = a * LH + k;  // lane 1: rows LH .. P - 1
+        if (l < P) {
+            double2 r = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int m = 0; m < P; ++m) cfma(r, e1[m], cvt<double2>(w[l * P + m]));
+            const double2 wl = (LH + k < P && a) ? e0[LH + k < P ? LH + k : 0] : e0[k];
+            cfma(acc, wl, r);
+        }
+    }
+    const double2 o = make_double2(__shfl_xor(acc.x, 1), __shfl_xor(acc.y, 1));
+    if (a == 0 && i0 < nx) u[i0] = make_double2(acc.x + o.x, acc.y + o.y);
 }
 
 template <int D, int P, typename S>
@@ -818,13 +884,13 @@ void launch_final(const Launch &c, const void *state, const Tree &tx, double, in
     const bool f32 = c.precision != BFSFT_FP64;
     dispatch_p(c.p, [&](auto tag) {
         constexpr int P = decltype(tag)::value;
-        if (c.d == 2) {
+        if (c.d == 2) {  // two lanes per target (k_final2)
             if (f32)
-                k_final<2, P, float><<<nblk(nx, 256), 256, 0, c.stream>>>(
+                k_final2<P, float><<<nblk(2 * nx, 256), 256, 0, c.stream>>>(
                     nx, (const float2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
                     c.tb->node_turns, (const double2 *)c.tb->erot, (double2 *)u);
             else
-                k_final<2, P, double><<<nblk(nx, 256), 256, 0, c.stream>>>(
+                k_final2<P, double><<<nblk(2 * nx, 256), 256, 0, c.stream>>>(
                     nx, (const double2 *)state, tx.leaf_of, tx.local, (const double2 *)c.tb->bary,
                     c.tb->node_turns, (const double2 *)c.tb->erot, (double2 *)u);
         } else if constexpr (P <= 8) {
