@@ -265,13 +265,14 @@ int bfsft_execute_batched_serial(bfsft_plan *plan, const double *f_packed, doubl
 /*
  * Kernel timing (measurement).  bfsft_timing_begin arms HIP events for the
  * next `max_execs` executes of a single-transform plan: each records events on
- * the plan stream before the leaf launch, after it, after every translation
- * launch and after the final launch.  bfsft_timing_end waits for them, then
- * writes to out (host, n doubles):
+ * the plan stream before the start-level launch (leaf initialisation or direct
+ * sums), after it, after every translation launch and after the final launch.
+ * bfsft_timing_end waits for them, then writes to out (host, n doubles):
  *   out[0]      executes recorded
- *   out[1]      leaf initialisation, ms summed over executes
+ *   out[1]      leaf initialisation or start-level direct sums, ms summed over executes
  *   out[2]      final evaluation, ms summed
- *   out[3 + l]  translation launch producing T_K level l (l = 0..L-1), ms summed
+ *   out[3 + l]  translation launch producing T_K level l (l = 0..L-1), ms summed;
+ *               0 for the levels at and above the start level (no launch)
  * and disarms timing.  Returns BFSFT_EINVAL if n < 3 + L.
  */
 int bfsft_timing_begin(bfsft_plan *plan, int max_execs);
