@@ -272,7 +272,8 @@ int bfsft_execute_batched_serial(bfsft_plan *plan, const double *f_packed, doubl
  *   out[1]      leaf initialisation or start-level direct sums, ms summed over executes
  *   out[2]      final evaluation, ms summed
  *   out[3 + l]  translation launch producing T_K level l (l = 0..L-1), ms summed;
- *               0 for the levels at and above the start level (no launch)
+ *               0 for l >= L - s0 (s0 the start level: those levels have no
+ *               translation launch)
  * and disarms timing.  Returns BFSFT_EINVAL if n < 3 + L.
  */
 int bfsft_timing_begin(bfsft_plan *plan, int max_execs);
