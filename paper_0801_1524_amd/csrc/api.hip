@@ -299,7 +299,7 @@ int first_kind(int choices) { return (choices & 1) ? 0 : (choices & 2) ? 1 : 2; 
 void autotune_single(bfsft_plan *P)
 {
     const int choices = kernel_choices(P);
-    const std::string key = "single4/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
+    const std::string key = "single5/d" + std::to_string(P->d) + "/p" + std::to_string(P->p) + "/" +
                             prec_name(P->precision) + "/L" + std::to_string(P->L) + "/k" +
                             std::to_string(choices);
     std::vector<int> v;
@@ -319,7 +319,7 @@ void autotune_single(bfsft_plan *P)
     BF_HIP(hipMemsetAsync(P->buf[1], 0, bytes, P->stream));
     // budgets a few KB apart: the threads a tile fills depend on them finely;
     // 2D also tries tiles of two work-groups per CU (kLdsMax2D)
-    std::vector<int> cand = {8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 54, 60};
+    std::vector<int> cand = {8, 12, 16, 20, 24, 28, 30, 32, 34, 36, 38, 40, 44, 48, 54, 60};
     if (P->d == 2) cand.insert(cand.end(), {66, 72, 76});
     std::vector<double> best(P->L, 1e30);
     std::vector<int> pick(P->L, 32), pk(P->L, first_kind(choices));
