@@ -135,7 +135,8 @@ typedef struct {
  * on the points only ((nA + p^d) x 16 bytes per source) when they fit
  * BFSFT_DIRECT_TABLE_MB (default 2048; 0: computed at every execute);
  * BFSFT_TUNE_CACHE names the text file caching tuned choices (default
- * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget.
+ * $HOME/.cache/bfsft_tune.txt); BFSFT_LDS_KB sets the untuned tile budget (8-76 KB in
+ * 2D, 8-60 KB in 3D; other values give 32 KB).
  */
 int bfsft_plan_create(bfsft_plan **out, int d, int64_t N, int p, int precision,
                       const double *x, int64_t nx, const double *k, int64_t nk,

@@ -431,7 +431,7 @@ void build_tiles_levels(bfsft_plan *P, const std::vector<int> &lds_bytes, const 
 {
     P->lds_level = lds_bytes;
     P->kind = kinds.empty() ? std::vector<int>(P->L, 0) : kinds;
-    P->lds = lds_bytes.empty() ? translate_default_lds() : lds_bytes[0];
+    P->lds = lds_bytes.empty() ? translate_default_lds(P->d) : lds_bytes[0];
     P->tiles.assign(P->L, nullptr);
     P->ntile.assign(P->L, 0);
     P->cost_max.assign(P->L, 0);
@@ -571,7 +571,7 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     build_tables(P->tb, P->p, P->N, P->L, P->arena, s);
     P->sig.assign(P->L, nullptr);
     if (P->nx == 0 || P->nk == 0) {
-        build_tiles(P, translate_default_lds());
+        build_tiles(P, translate_default_lds(P->d));
         BF_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -589,7 +589,7 @@ void build_plan(bfsft_plan *P, const double *x, const double *k)
     build_start(P->start, P->tk, sc.s0, P->d, P->p - 1, P->rho, P->arena, s);
     if (P->start.kind == 1 && P->start.s0 > 0)
         build_direct_steps(P->start, P->tx, P->tk, P->tb, P->d, P->p, P->N, P->arena, s);
-    build_tiles(P, translate_default_lds());
+    build_tiles(P, translate_default_lds(P->d));
     BF_HIP(hipStreamSynchronize(s));
 }
 
@@ -638,7 +638,7 @@ bfsft_plan *make_adjoint(bfsft_plan *P)
             if (A->start.kind == 1 && A->start.s0 > 0)
                 build_direct_steps(A->start, A->tx, A->tk, A->tb, A->d, A->p, A->N, A->arena, A->stream);
         }
-        build_tiles(A, translate_default_lds());
+        build_tiles(A, translate_default_lds(A->d));
         if (A->nx > 0 && A->nk > 0 && autotune_enabled()) autotune_single(A);
         BF_HIP(hipStreamSynchronize(A->stream));
     } catch (...) {

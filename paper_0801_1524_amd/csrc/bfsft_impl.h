@@ -129,7 +129,7 @@ struct Launch {
     hipStream_t stream;
 };
 
-int translate_default_lds();
+int translate_default_lds(int d);
 int translate_cap_blocks(int d, int p, int precision, int budget);
 int translate_tile_cost(int d, int p, int precision, int nin, int nb, int kind = 0);
 bool translate_fits(int d, int p, int precision);

@@ -388,16 +388,19 @@ __global__ __launch_bounds__(kTT, (min_waves<D, P>())) void k_translate_batched_
         translate3d_item<P, false, S, C>(a, item - prefix[lo], smem);
 }
 
-int lds_budget_default()
+// BFSFT_LDS_KB if it names a budget the d-dimensional kernels can launch
+// (8 KB up to kLdsMax2D in 2D, kLdsMax in 3D), else 32 KB
+int lds_budget_default(int d)
 {
     const char *s = std::getenv("BFSFT_LDS_KB");
     const int v = s ? std::atoi(s) : 0;
-    return ((v >= 8 && v <= 64) ? v : 32) * 1024;
+    const int vmax = (int)((d == 2 ? kLdsMax2D : kLdsMax) / 1024);
+    return ((v >= 8 && v <= vmax) ? v : 32) * 1024;
 }
 
 }  // namespace
 
-int translate_default_lds() { return lds_budget_default(); }
+int translate_default_lds(int d) { return lds_budget_default(d); }
 
 // Blocks of axis-1 results per box of a 3D tile: both t1 (4) when a box
 // with all its children fits that way, else one t1 (2); the kernels take

@@ -135,7 +135,7 @@ def test_chunked_launches_match_one_launch(bf, monkeypatch, d, kernel):
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_tile_budgets_one_and_several_rows_per_thread(bf, oracle_mod, monkeypatch, d, precision):
-    """Untuned tiles at the smallest and the largest LDS budget.  At 8 KB a
+    """Untuned tiles at the smallest and the largest LDS budgets.  At 8 KB a
     tile's stage 1 has at most one input row per thread (no next row is
     loaded); at 60 KB several (the next row is loaded while the current one
     is computed, and in 3D the rows are loaded again for the second axis-2
@@ -150,12 +150,15 @@ def test_tile_budgets_one_and_several_rows_per_thread(bf, oracle_mod, monkeypatc
     monkeypatch.setenv("BFSFT_AUTOTUNE", "0")
     ref = oracle_u(oracle_mod, P)
     us = []
-    for kb in ("8", "60"):
+    # 2D tiles may take 76 KB (two work-groups per CU); in 3D a budget above
+    # 60 KB is not taken (the default 32 KB is used instead)
+    for kb in (("8", "60", "76") if d == 2 else ("8", "60", "64")):
         monkeypatch.setenv("BFSFT_LDS_KB", kb)
         u = gpu_u(bf, P, precision)
         check_o2(rel_l2(u, ref), case, precision)
         us.append(u)
-    assert rel_l2(us[0], us[1]) <= 1e-14
+    for u in us[1:]:
+        assert rel_l2(us[0], u) <= 1e-14
 
 
 def test_deterministic(bf):
